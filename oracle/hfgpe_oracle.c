@@ -1,0 +1,621 @@
+/*
+ * hfgpe_oracle.c -- plain, slow FP64 CPU oracle for the Hermite-Fourier
+ * split-step integrator of
+ *   P. Bader and S. Blanes, "Fourier methods for the perturbed harmonic
+ *   oscillator in linear and nonlinear Schroedinger equations" (arXiv:1007.3470).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg use it.  It shares no code, header, table or helper with the
+ * GPU library.
+ *
+ * What it computes (each function cites the passage it follows):
+ *   - the periodic equidistant grid x_i = a + i (b-a)/N (Sec. 1, Eq. GP1ODE);
+ *   - its own iterative radix-2 FFT, twiddles evaluated directly with cos/sin
+ *     (the discrete Fourier transform of Sec. 2.1, Eq. GP1ODE_T);
+ *   - the harmonic-oscillator stage coefficients by the "2x2 route": the
+ *     classical (Heisenberg) matrix S of the stage propagator is built first
+ *     (exact constant-frequency flow, the two-exponential commutator-free
+ *     product of Eq. CommutatorFree, or the exponential of the sixth-order
+ *     Magnus generator of Sec. 4.2) and then factored as
+ *     S = K(f) D(g) K(e), i.e. g = S12, e = (1-S11)/g, f = (1-S22)/g, which is
+ *     the content of Lemma 2 and Theorems 1-2 (Sec. 2.2);
+ *   - one time step as Table "algorithm" of Sec. 2 with the HO split (ii):
+ *     the B flow (Lemma 1, frozen time) and the A flow = K(f) D(g) K(e),
+ *     applied one after the other WITHOUT merging adjacent x-phases (the
+ *     GPU library merges them; the unmerged order is the cross-check);
+ *   - norm and energy observables (Sec. 1).
+ *
+ * Conventions (readings where the paper is silent):
+ *   forward DFT  u^_q = sum_n u_n exp(-2 pi i q n / N)   (unnormalised)
+ *   inverse DFT  u_n  = (1/N) sum_q u^_q exp(+2 pi i q n / N)
+ *   k_q = 2 pi / L * (q < N/2 ? q : q - N)
+ *   K(c): u(x) <- exp(-i c x^2/2) u(x);  D(g): u^(k) <- exp(-i g k^2/2) u^(k)
+ *   B_w(tau): u <- exp(-i h w (eps V_I(x) + sigma(tau) |u|^2)) u
+ *
+ * Parameter block (doubles, ORC_NPAR per instance):
+ *   [0]            mu
+ *   [1+4j..4+4j]   omega0, omega_amp, omega_freq, omega_phase of axis j
+ *                  omega_j(t) = omega0 (1 + amp sin(freq t + phase))
+ *   [13..16]       sigma0, sigma_amp, sigma_freq, sigma_phase (same form)
+ *   [17]           eps
+ *   [18+6j..23+6j] V_I factor of axis j: c0, c2, c4, gs, k, phi
+ *                  v_j(x) = (c0 + c2 x^2 + c4 x^4) * (gs > 0 ? exp(-x^2/gs) : 1)
+ *                           * cos(k x + phi);   V_I = prod_j v_j(x_j)
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared -lm
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_NPAR 36
+#define ORC_PI 3.14159265358979323846
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ESINGULAR = -2, ORC_EFREQ = -3, ORC_ENOMEM = -4 };
+enum { ORC_HO_EXACT_CONST = 0, ORC_HO_CF4 = 1, ORC_HO_MAGNUS6 = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* Parameter access                                                          */
+/* ------------------------------------------------------------------------ */
+
+static double par_mu(const double *p) { return p[0]; }
+
+/* omega_j(t) of the trap, Eq. GP1b with a time-dependent frequency. */
+static double par_omega(const double *p, int j, double t)
+{
+    const double *w = p + 1 + 4 * j;
+    return w[0] * (1.0 + w[1] * sin(w[2] * t + w[3]));
+}
+
+/* sigma(t) of the mean-field term, Sec. 1. */
+static double par_sigma(const double *p, double t)
+{
+    const double *s = p + 13;
+    return s[0] * (1.0 + s[1] * sin(s[2] * t + s[3]));
+}
+
+static double par_eps(const double *p) { return p[17]; }
+
+/* One separable factor of the perturbing potential V_I. */
+static double vfactor(const double *p, int j, double x)
+{
+    const double *v = p + 18 + 6 * j;
+    double poly = v[0] + v[1] * x * x + v[2] * x * x * x * x;
+    double gauss = (v[3] > 0.0) ? exp(-x * x / v[3]) : 1.0;
+    return poly * gauss * cos(v[4] * x + v[5]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* FFT: iterative radix-2, bit reversal first, twiddles by direct cos/sin.  */
+/* ------------------------------------------------------------------------ */
+
+static int is_pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
+
+/* Twiddle table tw[q] = exp(-2 pi i q / n), q < n/2, each entry evaluated
+ * directly (no recurrences). */
+static double *make_twiddles(int n)
+{
+    int half = n / 2 > 0 ? n / 2 : 1;
+    double *tw = (double *)malloc(sizeof(double) * 2 * half);
+    if (!tw) return NULL;
+    for (int q = 0; q < half; ++q) {
+        double ang = -2.0 * ORC_PI * (double)q / (double)n;
+        tw[2 * q] = cos(ang);
+        tw[2 * q + 1] = sin(ang);
+    }
+    return tw;
+}
+
+/* In-place FFT of a contiguous complex vector z (interleaved re, im).
+ * sign = -1 forward (unnormalised), +1 inverse (scaled by 1/n). */
+static void fft_contig(int n, double *z, int sign, const double *tw)
+{
+    if (n <= 1) return;
+    /* bit-reversal permutation */
+    for (int i = 1, j = 0; i < n; ++i) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            double tr = z[2 * i], ti = z[2 * i + 1];
+            z[2 * i] = z[2 * j];
+            z[2 * i + 1] = z[2 * j + 1];
+            z[2 * j] = tr;
+            z[2 * j + 1] = ti;
+        }
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        int half = len / 2, step = n / len;
+        for (int s = 0; s < n; s += len) {
+            for (int q = 0; q < half; ++q) {
+                double wr = tw[2 * q * step];
+                double wi = tw[2 * q * step + 1];
+                if (sign > 0) wi = -wi;
+                double *u = z + 2 * (s + q);
+                double *v = z + 2 * (s + q + half);
+                double vr = v[0] * wr - v[1] * wi;
+                double vi = v[0] * wi + v[1] * wr;
+                v[0] = u[0] - vr;
+                v[1] = u[1] - vi;
+                u[0] = u[0] + vr;
+                u[1] = u[1] + vi;
+            }
+        }
+    }
+    if (sign > 0) {
+        double inv = 1.0 / (double)n;
+        for (int i = 0; i < 2 * n; ++i) z[i] *= inv;
+    }
+}
+
+/* FFT along one axis of a row-major d-D array (x fastest).  n[0] is the x
+ * extent, n[1] y, n[2] z.  Each pencil is copied out, transformed, copied
+ * back. */
+static int fft_axis(const int n[3], int axis, double *z, int sign)
+{
+    int len = n[axis];
+    if (len <= 1) return ORC_OK;
+    long stride = 1;
+    for (int j = 0; j < axis; ++j) stride *= n[j];
+    long total = (long)n[0] * n[1] * n[2];
+    long npencil = total / len;
+    double *tw = make_twiddles(len);
+    double *buf = (double *)malloc(sizeof(double) * 2 * len);
+    if (!tw || !buf) { free(tw); free(buf); return ORC_ENOMEM; }
+    for (long pidx = 0; pidx < npencil; ++pidx) {
+        /* pencil start: split pidx into (outer, inner) around the axis */
+        long inner = pidx % stride, outer = pidx / stride;
+        long base = outer * stride * len + inner;
+        for (int i = 0; i < len; ++i) {
+            buf[2 * i] = z[2 * (base + i * stride)];
+            buf[2 * i + 1] = z[2 * (base + i * stride) + 1];
+        }
+        fft_contig(len, buf, sign, tw);
+        for (int i = 0; i < len; ++i) {
+            z[2 * (base + i * stride)] = buf[2 * i];
+            z[2 * (base + i * stride) + 1] = buf[2 * i + 1];
+        }
+    }
+    free(tw);
+    free(buf);
+    return ORC_OK;
+}
+
+/* d-D FFT = 1-D FFT along every axis. */
+int orc_fftn(int ndim, const int *n_in, double *z, int sign)
+{
+    int n[3] = {1, 1, 1};
+    if (ndim < 1 || ndim > 3) return ORC_EINVAL;
+    for (int j = 0; j < ndim; ++j) {
+        if (!is_pow2(n_in[j])) return ORC_EINVAL;
+        n[j] = n_in[j];
+    }
+    for (int j = 0; j < ndim; ++j) {
+        int rc = fft_axis(n, j, z, sign);
+        if (rc) return rc;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2x2 route for the harmonic-oscillator stage coefficients                 */
+/* ------------------------------------------------------------------------ */
+
+/* The 2x2 matrices of this section are held in "deviation form"
+ * X = S - I, so that 1 - S11 and 1 - S22, which the factorisation divides by
+ * S12, come out without the cancellation 1 - cos(w tau) would suffer for
+ * small steps.  cos(x) - 1 is evaluated as -2 sin^2(x/2). */
+static double cosm1(double x)
+{
+    double s = sin(0.5 * x);
+    return -2.0 * s * s;
+}
+
+/* Product in deviation form: (I + A)(I + B) = I + A + B + A B. */
+static void dev_mul(const double A[4], const double B[4], double C[4])
+{
+    double c0 = A[0] + B[0] + (A[0] * B[0] + A[1] * B[2]);
+    double c1 = A[1] + B[1] + (A[0] * B[1] + A[1] * B[3]);
+    double c2 = A[2] + B[2] + (A[2] * B[0] + A[3] * B[2]);
+    double c3 = A[3] + B[3] + (A[2] * B[1] + A[3] * B[3]);
+    C[0] = c0; C[1] = c1; C[2] = c2; C[3] = c3;
+}
+
+/* Classical flow over time tau of H = p^2/(2 mu) + mu q x^2 / 2 (q = omega^2
+ * held fixed), acting on (x, p): x' = p/mu, p' = -mu q x.  This is the exact
+ * HO evolution matrix of Lemma 2's proof, generalised to mu.  Deviation form. */
+static int ho_flow(double q, double mu, double tau, double X[4])
+{
+    if (!(q > 0.0)) return ORC_EFREQ;
+    double w = sqrt(q);
+    double cm = cosm1(w * tau), s = sin(w * tau);
+    X[0] = cm;
+    X[1] = s / (mu * w);
+    X[2] = -mu * w * s;
+    X[3] = cm;
+    return ORC_OK;
+}
+
+/* Fourth-order commutator-free approximation, Eq. CommutatorFree: the
+ * product of two constant-frequency half-step flows with Gauss-averaged
+ * squared frequencies.  The right factor (weighted toward the earlier node)
+ * acts first, so S = M(omega_L^2) M(omega_R^2). */
+static int ho_cf4(const double *p, int axis, double t0, double tau, double X[4])
+{
+    double c1 = 0.5 - sqrt(3.0) / 6.0, c2 = 0.5 + sqrt(3.0) / 6.0;
+    double al = 0.5 - 1.0 / sqrt(3.0), be = 1.0 - al;
+    double w1 = par_omega(p, axis, t0 + c1 * tau);
+    double w2 = par_omega(p, axis, t0 + c2 * tau);
+    double qL = al * w1 * w1 + be * w2 * w2;
+    double qR = be * w1 * w1 + al * w2 * w2;
+    double ML[4], MR[4];
+    int rc = ho_flow(qL, par_mu(p), 0.5 * tau, ML);
+    if (rc) return rc;
+    rc = ho_flow(qR, par_mu(p), 0.5 * tau, MR);
+    if (rc) return rc;
+    dev_mul(ML, MR, X);
+    return ORC_OK;
+}
+
+/* Sixth-order Magnus approximation of Sec. 4.2: exponent
+ * -i (tau/2)(alpha x^2 + beta (xp+px) + gamma p^2) with the three-node Gauss
+ * rule on the stage interval [t0, t0+tau]; the omega_i of the printed
+ * formulas are read as squared frequencies at the nodes.  The formulas are
+ * for mu = 1; other mu go through the canonical scaling X = sqrt(mu) x,
+ * P = p / sqrt(mu).  Deviation form. */
+static int ho_magnus6(const double *p, int axis, double t0, double tau, double X[4])
+{
+    double c1 = 0.5 - sqrt(15.0) / 10.0, c2 = 0.5, c3 = 0.5 + sqrt(15.0) / 10.0;
+    double a1 = par_omega(p, axis, t0 + c1 * tau);
+    double a2 = par_omega(p, axis, t0 + c2 * tau);
+    double a3 = par_omega(p, axis, t0 + c3 * tau);
+    double w1 = a1 * a1, w2 = a2 * a2, w3 = a3 * a3;
+    double tt = tau * tau;
+    double alpha = (5.0 * w1 + 8.0 * w2 + 5.0 * w3) / 18.0
+                 + tt / 486.0 * (17.0 / 4.0 * (w1 * w1 + w3 * w3) + 8.0 * w2 * w2
+                                 + w1 * w2 + w2 * w3 - 37.0 / 2.0 * w1 * w3);
+    double beta = tau * sqrt(5.0 / 3.0) * (w3 - w1)
+                * (1.0 / 12.0 + tt / 3240.0 * (5.0 * w1 + 8.0 * w2 + 5.0 * w3));
+    double gamma = 1.0 + tt / 54.0 * (w1 - 2.0 * w2 + w3);
+    /* Classical generator of H = (alpha x^2 + 2 beta x p + gamma p^2)/2:
+     * x' = beta x + gamma p, p' = -alpha x - beta p.  Its square is
+     * -(alpha gamma - beta^2) I, so exp(tau G) = cos(eta tau) I + sin(eta tau)/eta G. */
+    double eta2 = alpha * gamma - beta * beta;
+    if (!(eta2 > 0.0)) return ORC_EFREQ;
+    double eta = sqrt(eta2);
+    double cm = cosm1(eta * tau), s = sin(eta * tau) / eta;
+    /* back to the physical frame: x = X / sqrt(mu), p = sqrt(mu) P */
+    double mu = par_mu(p);
+    X[0] = cm + s * beta;
+    X[1] = s * gamma / mu;
+    X[2] = -s * alpha * mu;
+    X[3] = cm - s * beta;
+    return ORC_OK;
+}
+
+/* Stage matrix (deviation form) for one axis over [t0, t0 + tau]. */
+static int ho_stage_matrix(int rule, const double *p, int axis, double t0, double tau, double S[4])
+{
+    switch (rule) {
+    case ORC_HO_EXACT_CONST: {
+        double w = par_omega(p, axis, t0);
+        return ho_flow(w * w, par_mu(p), tau, S);
+    }
+    case ORC_HO_CF4:
+        return ho_cf4(p, axis, t0, tau, S);
+    case ORC_HO_MAGNUS6:
+        return ho_magnus6(p, axis, t0, tau, S);
+    default:
+        return ORC_EINVAL;
+    }
+}
+
+/* Factor a symplectic 2x2 matrix S = I + X as K(f) D(g) K(e) (rightmost
+ * first), with K(c) = [[1,0],[-c,1]] and D(g) = [[1,g],[0,1]]:
+ * K(f) D(g) K(e) = [[1 - g e, g], [-f - e + f g e, 1 - f g]], hence
+ * g = S12, e = (1 - S11)/g, f = (1 - S22)/g. */
+static int factor_kdk(const double X[4], double *f, double *g, double *e)
+{
+    double gg = X[1];
+    if (!(fabs(gg) > 1e-300) || !isfinite(gg)) return ORC_ESINGULAR;
+    *g = gg;
+    *e = -X[0] / gg;
+    *f = -X[3] / gg;
+    return ORC_OK;
+}
+
+/* Public: the 2x2 stage matrix S (not the deviation) for tests. */
+int orc_stage_matrix(int rule, const double *par, int axis, double t0, double tau, double *S)
+{
+    int rc = ho_stage_matrix(rule, par, axis, t0, tau, S);
+    if (rc) return rc;
+    S[0] += 1.0;
+    S[3] += 1.0;
+    return ORC_OK;
+}
+
+/* Public: (f, g, e) of every stage and axis of the step starting at tn.
+ * out[(i*ndim + j)*3 + {0,1,2}] = f, g, e of stage i, axis j. */
+int orc_stage_coeffs(int ndim, const double *par, int m, const double *a, int rule,
+                     double dt, double tn, double *out)
+{
+    double tau = tn;
+    for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < ndim; ++j) {
+            double X[4];
+            int rc = ho_stage_matrix(rule, par, j, tau, a[i] * dt, X);
+            if (rc) return rc;
+            rc = factor_kdk(X, &out[(i * ndim + j) * 3 + 0], &out[(i * ndim + j) * 3 + 1],
+                            &out[(i * ndim + j) * 3 + 2]);
+            if (rc) return rc;
+        }
+        tau = tau + a[i] * dt;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pointwise flows and the time step                                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int ndim;
+    int n[3];
+    double lo[3], dx[3];
+    long total;
+    const double *par;
+    double *vi;   /* eps * V_I at every grid point */
+    double *x2h;  /* per-axis x_j^2 / 2 tables, concatenated */
+    double *k2h;  /* per-axis k_j^2 / 2 tables, concatenated */
+} grid_t;
+
+static long axis_index(const grid_t *G, long idx, int axis)
+{
+    long s = 1;
+    for (int j = 0; j < axis; ++j) s *= G->n[j];
+    return (idx / s) % G->n[axis];
+}
+
+static int grid_init(grid_t *G, int ndim, const int *n, const double *lo, const double *hi,
+                     const double *par)
+{
+    memset(G, 0, sizeof(*G));
+    if (ndim < 1 || ndim > 3) return ORC_EINVAL;
+    G->ndim = ndim;
+    G->par = par;
+    G->total = 1;
+    int off = 0;
+    for (int j = 0; j < 3; ++j) {
+        G->n[j] = (j < ndim) ? n[j] : 1;
+        if (!is_pow2(G->n[j])) return ORC_EINVAL;
+        G->lo[j] = (j < ndim) ? lo[j] : 0.0;
+        G->dx[j] = (j < ndim) ? (hi[j] - lo[j]) / (double)G->n[j] : 1.0;
+        G->total *= G->n[j];
+        off += G->n[j];
+    }
+    G->vi = (double *)malloc(sizeof(double) * G->total);
+    G->x2h = (double *)malloc(sizeof(double) * off);
+    G->k2h = (double *)malloc(sizeof(double) * off);
+    if (!G->vi || !G->x2h || !G->k2h) return ORC_ENOMEM;
+    off = 0;
+    for (int j = 0; j < 3; ++j) {
+        double L = G->dx[j] * G->n[j];
+        for (int i = 0; i < G->n[j]; ++i) {
+            double x = (j < ndim) ? G->lo[j] + i * G->dx[j] : 0.0;
+            int q = (i < G->n[j] / 2) ? i : i - G->n[j];
+            double k = (j < ndim) ? 2.0 * ORC_PI / L * q : 0.0;
+            G->x2h[off + i] = 0.5 * x * x;
+            G->k2h[off + i] = 0.5 * k * k;
+        }
+        off += G->n[j];
+    }
+    double eps = par_eps(par);
+    for (long idx = 0; idx < G->total; ++idx) {
+        double v = 1.0;
+        for (int j = 0; j < ndim; ++j) {
+            long i = axis_index(G, idx, j);
+            v *= vfactor(par, j, G->lo[j] + i * G->dx[j]);
+        }
+        G->vi[idx] = eps * v;
+    }
+    return ORC_OK;
+}
+
+static void grid_free(grid_t *G)
+{
+    free(G->vi);
+    free(G->x2h);
+    free(G->k2h);
+}
+
+static const double *axis_table(const grid_t *G, const double *tab, int axis)
+{
+    int off = 0;
+    for (int j = 0; j < axis; ++j) off += G->n[j];
+    return tab + off;
+}
+
+static void mul_phase(double *z, double theta)
+{
+    /* z <- exp(-i theta) z */
+    double c = cos(theta), s = sin(theta);
+    double re = z[0] * c + z[1] * s;
+    double im = z[1] * c - z[0] * s;
+    z[0] = re;
+    z[1] = im;
+}
+
+/* B flow frozen at time tau with weight w (Lemma 1; Table "algorithm"):
+ * u <- exp(-i dt w (eps V_I + sigma(tau) |u|^2)) u. */
+static void apply_B(const grid_t *G, double *u, double dt, double w, double tau)
+{
+    if (w == 0.0) return;
+    double sig = par_sigma(G->par, tau);
+    for (long idx = 0; idx < G->total; ++idx) {
+        double a2 = u[2 * idx] * u[2 * idx] + u[2 * idx + 1] * u[2 * idx + 1];
+        mul_phase(u + 2 * idx, dt * w * (G->vi[idx] + sig * a2));
+    }
+}
+
+/* Kick K(c): u <- exp(-i sum_j c_j x_j^2 / 2) u. */
+static void apply_K(const grid_t *G, double *u, const double *c)
+{
+    for (long idx = 0; idx < G->total; ++idx) {
+        double th = 0.0;
+        for (int j = 0; j < G->ndim; ++j)
+            th += c[j] * axis_table(G, G->x2h, j)[axis_index(G, idx, j)];
+        mul_phase(u + 2 * idx, th);
+    }
+}
+
+/* Drift D(g): d-D FFT, multiply by exp(-i sum_j g_j k_j^2/2), inverse FFT
+ * (Eq. GP1ODE_T and its solution). */
+static int apply_D(const grid_t *G, double *u, const double *g)
+{
+    int rc = orc_fftn(G->ndim, G->n, u, -1);
+    if (rc) return rc;
+    for (long idx = 0; idx < G->total; ++idx) {
+        double th = 0.0;
+        for (int j = 0; j < G->ndim; ++j)
+            th += g[j] * axis_table(G, G->k2h, j)[axis_index(G, idx, j)];
+        mul_phase(u + 2 * idx, th);
+    }
+    return orc_fftn(G->ndim, G->n, u, +1);
+}
+
+/* One step t_n -> t_n + dt of the composition (Eq. prod-gen, Table
+ * "algorithm"), with each A flow replaced by its K(f) D(g) K(e) factorisation.
+ * b holds m+1 weights (BAB form; b[0] = 0 gives an ABA-type scheme). */
+static int step_once(const grid_t *G, double *u, int m, const double *a, const double *b,
+                     int rule, double dt, double tn)
+{
+    double tau = tn;
+    apply_B(G, u, dt, b[0], tau);
+    for (int i = 0; i < m; ++i) {
+        double f[3], g[3], e[3];
+        for (int j = 0; j < G->ndim; ++j) {
+            double X[4];
+            int rc = ho_stage_matrix(rule, G->par, j, tau, a[i] * dt, X);
+            if (rc) return rc;
+            rc = factor_kdk(X, &f[j], &g[j], &e[j]);
+            if (rc) return rc;
+        }
+        apply_K(G, u, e);
+        int rc = apply_D(G, u, g);
+        if (rc) return rc;
+        apply_K(G, u, f);
+        tau = tau + a[i] * dt;
+        apply_B(G, u, dt, b[i + 1], tau);
+    }
+    return ORC_OK;
+}
+
+/* Public: evolve one instance nsteps steps from t0.  psi is interleaved
+ * complex (re, im) in row-major order with x fastest. */
+int orc_evolve(int ndim, const int *n, const double *lo, const double *hi, const double *par,
+               int m, const double *a, const double *b, int rule, double dt, double t0,
+               long nsteps, double *psi)
+{
+    if (m < 1 || nsteps < 0) return ORC_EINVAL;
+    grid_t G;
+    int rc = grid_init(&G, ndim, n, lo, hi, par);
+    if (rc) { grid_free(&G); return rc; }
+    for (long s = 0; s < nsteps && rc == ORC_OK; ++s)
+        rc = step_once(&G, psi, m, a, b, rule, dt, t0 + (double)s * dt);
+    grid_free(&G);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Observables                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Neumaier-compensated accumulator. */
+typedef struct { double s, c; } ksum_t;
+static void ksum_add(ksum_t *k, double v)
+{
+    double t = k->s + v;
+    if (fabs(k->s) >= fabs(v)) k->c += (k->s - t) + v;
+    else k->c += (v - t) + k->s;
+    k->s = t;
+}
+static double ksum_val(const ksum_t *k) { return k->s + k->c; }
+
+/* Discrete L2 norm squared: h^d sum |u|^2 (the preserved norm of Sec. 1). */
+int orc_norm(int ndim, const int *n, const double *lo, const double *hi, const double *psi,
+             double *out)
+{
+    double cell = 1.0;
+    long total = 1;
+    for (int j = 0; j < ndim; ++j) {
+        if (!is_pow2(n[j])) return ORC_EINVAL;
+        cell *= (hi[j] - lo[j]) / (double)n[j];
+        total *= n[j];
+    }
+    ksum_t acc = {0.0, 0.0};
+    for (long idx = 0; idx < total; ++idx)
+        ksum_add(&acc, psi[2 * idx] * psi[2 * idx] + psi[2 * idx + 1] * psi[2 * idx + 1]);
+    *out = cell * ksum_val(&acc);
+    return ORC_OK;
+}
+
+/* Energy of the GPE (Sec. 1):
+ *   E = h^d [ (1/Ntot) sum_k |k|^2/(2 mu) |u^_k|^2
+ *             + sum_x (V(x,t) |u|^2 + sigma(t)/2 |u|^4) ],
+ *   V = sum_j mu omega_j(t)^2 x_j^2 / 2 + eps V_I(x).
+ * out[0..3] = total, kinetic, potential, interaction. */
+int orc_energy(int ndim, const int *n, const double *lo, const double *hi, const double *par,
+               double t, const double *psi, double *out)
+{
+    grid_t G;
+    int rc = grid_init(&G, ndim, n, lo, hi, par);
+    if (rc) { grid_free(&G); return rc; }
+    double cell = 1.0;
+    for (int j = 0; j < ndim; ++j) cell *= G.dx[j];
+    double *uh = (double *)malloc(sizeof(double) * 2 * G.total);
+    if (!uh) { grid_free(&G); return ORC_ENOMEM; }
+    memcpy(uh, psi, sizeof(double) * 2 * G.total);
+    rc = orc_fftn(ndim, G.n, uh, -1);
+    if (rc) { free(uh); grid_free(&G); return rc; }
+    double mu = par_mu(par), sig = par_sigma(par, t);
+    ksum_t kin = {0, 0}, pot = {0, 0}, inter = {0, 0};
+    for (long idx = 0; idx < G.total; ++idx) {
+        double k2h = 0.0, vh = 0.0;
+        for (int j = 0; j < ndim; ++j) {
+            long i = axis_index(&G, idx, j);
+            double w = par_omega(par, j, t);
+            k2h += axis_table(&G, G.k2h, j)[i];
+            vh += mu * w * w * axis_table(&G, G.x2h, j)[i];
+        }
+        double a2h = uh[2 * idx] * uh[2 * idx] + uh[2 * idx + 1] * uh[2 * idx + 1];
+        ksum_add(&kin, k2h / mu * a2h);
+        double a2 = psi[2 * idx] * psi[2 * idx] + psi[2 * idx + 1] * psi[2 * idx + 1];
+        ksum_add(&pot, (vh + G.vi[idx]) * a2);
+        ksum_add(&inter, 0.5 * sig * a2 * a2);
+    }
+    out[1] = cell * ksum_val(&kin) / (double)G.total;
+    out[2] = cell * ksum_val(&pot);
+    out[3] = cell * ksum_val(&inter);
+    out[0] = out[1] + out[2] + out[3];
+    free(uh);
+    grid_free(&G);
+    return ORC_OK;
+}
+
+int orc_npar(void) { return ORC_NPAR; }
+
+/* Public (tests): apply the drift D(g) alone to one instance. */
+int orc_drift(int ndim, const int *n, const double *lo, const double *hi, const double *g,
+              double *psi)
+{
+    double par[ORC_NPAR];
+    memset(par, 0, sizeof(par));
+    par[0] = 1.0;
+    for (int j = 0; j < 3; ++j) par[18 + 6 * j] = 1.0;
+    grid_t G;
+    int rc = grid_init(&G, ndim, n, lo, hi, par);
+    if (rc == ORC_OK) rc = apply_D(&G, psi, g);
+    grid_free(&G);
+    return rc;
+}
