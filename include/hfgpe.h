@@ -1,0 +1,193 @@
+/*
+ * hfgpe.h -- C ABI of the MI355X Hermite-Fourier GPE time-stepping library.
+ *
+ * Method: P. Bader and S. Blanes, "Fourier methods for the perturbed harmonic
+ * oscillator in linear and nonlinear Schroedinger equations" (arXiv:1007.3470).
+ *
+ * The library advances, on one AMD Instinct MI355X (gfx950), a batch of
+ * independent solutions of the Gross-Pitaevskii equation (Sec. 1)
+ *
+ *   i psi_t = ( p^2/(2 mu) + sum_j mu omega_j(t)^2 x_j^2 / 2
+ *               + eps V_I(x) + sigma(t) |psi|^2 ) psi,      x in R^d, d <= 3,
+ *
+ * with the Hermite-Fourier splitting methods of Sec. 3: the harmonic part
+ * H0(t) (Eq. GP1b) is propagated exactly (Lemma 2) or through the
+ * commutator-free / sixth-order Magnus approximations (Eq. CommutatorFree,
+ * Sec. 4.2) factored into a chirp, a kinetic phase in Fourier space and a
+ * chirp (Theorems 1 and 2); the rest, eps V_I + sigma |psi|^2, is a pointwise
+ * phase (Lemma 1).  A step of an m-stage composition (Eq. prod-gen with time
+ * frozen in B as in Table "algorithm") costs m FFT pairs because adjacent
+ * x-space phases are merged (Eq. leapfrogHF, Eq. prod-genHarmOsc).
+ *
+ * Conventions
+ *   - Grid (Eq. GP1ODE): x_{j,i} = lo_j + i (hi_j - lo_j)/n_j, i = 0..n_j-1,
+ *     periodic; n_j a power of two.
+ *   - Data: one packed device buffer of interleaved complex values
+ *     (float2 for HFGPE_C64, double2 for HFGPE_C128).  Instance k occupies
+ *     complex elements [off[k], off[k+1]) (see hfgpe_instance_offsets) in
+ *     row-major order with x fastest: element (ix, iy, iz) of instance k is
+ *     at off[k] + (iz * n_y + iy) * n_x + ix.
+ *   - Kinetic wavenumbers k_q = 2 pi / L * (q < n/2 ? q : q - n).
+ *   - Every function returns an int status: HFGPE_OK (0) or a negative code.
+ *     No exception crosses the ABI.  hfgpe_status_string() names a code.
+ *   - Ownership: the caller owns every buffer it passes; the plan owns its
+ *     device workspace and releases it in hfgpe_plan_destroy.
+ *   - Streams: a plan is bound to one HIP stream (NULL = the default stream)
+ *     and is not thread-safe; calls on one plan must not overlap.
+ */
+#ifndef HFGPE_H
+#define HFGPE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HFGPE_VERSION_MAJOR 0
+#define HFGPE_VERSION_MINOR 1
+
+/* Status codes. */
+#define HFGPE_OK 0
+#define HFGPE_E_INVALID_ARG (-1)       /* null pointer, bad count, bad scheme ... */
+#define HFGPE_E_UNSUPPORTED_SHAPE (-2) /* n_j not a power of two, or too large  */
+#define HFGPE_E_SINGULAR (-3)          /* |a_i dt| reaches the first zero of g  */
+#define HFGPE_E_NONPOSITIVE_FREQ (-4)  /* omega <= 0, omega_L^2 <= 0, eta^2 <= 0 */
+#define HFGPE_E_ALLOC (-5)             /* device or host allocation failed      */
+#define HFGPE_E_HIP (-6)               /* a HIP call failed; hfgpe_last_hip_error */
+#define HFGPE_E_NONFINITE (-7)         /* a coefficient came out NaN/Inf        */
+#define HFGPE_E_NO_DEVICE (-8)         /* no usable gfx950 device               */
+
+/* Largest grid extent per axis supported by the resident kernels. */
+#define HFGPE_MAX_N_1D 4096
+#define HFGPE_MAX_N_ND 1024
+
+typedef enum { HFGPE_C64 = 0, HFGPE_C128 = 1 } hfgpe_dtype;
+
+/* Rule for the harmonic-oscillator part of each stage (Sec. 2.2, 4.2). */
+typedef enum {
+    HFGPE_HO_EXACT_CONST = 0, /* Lemma 2; omega must be constant in time        */
+    HFGPE_HO_CF4 = 1,         /* Eq. CommutatorFree + Theorem 2 (order 4)       */
+    HFGPE_HO_MAGNUS6 = 2      /* sixth-order Magnus of Sec. 4.2 + Theorem 1     */
+} hfgpe_ho_rule;
+
+/* Uniform periodic grid of one instance. */
+typedef struct {
+    int ndim;      /* 1, 2 or 3 */
+    int n[3];      /* points per axis, powers of two; axes >= ndim must be 1 */
+    double lo[3];  /* box [lo_j, hi_j) per axis */
+    double hi[3];
+} hfgpe_grid;
+
+/* A positive quantity modulated in time: v(t) = v0 (1 + amp sin(freq t + phase)). */
+typedef struct {
+    double v0, amp, freq, phase;
+} hfgpe_sinmod;
+
+/* One separable factor of the perturbation V_I:
+ *   v(x) = (c0 + c2 x^2 + c4 x^4) * exp(-x^2 / gs) * cos(k x + phi),
+ * the Gaussian factor being omitted when gs <= 0.  V_I(x) = prod_j v_j(x_j). */
+typedef struct {
+    double c0, c2, c4, gs, k, phi;
+} hfgpe_vfactor;
+
+/* Physical parameters of one instance. */
+typedef struct {
+    double mu;              /* mass, > 0 */
+    hfgpe_sinmod omega[3];  /* trap frequency per axis (Eq. GP1b)  */
+    hfgpe_sinmod sigma;     /* mean-field coupling sigma(t) (Sec. 1); v0 may be
+                               negative (attractive) or zero (linear problem) */
+    double eps;             /* strength of V_I */
+    hfgpe_vfactor v[3];     /* V_I factors; set c0 = 1, rest 0, for "no factor" */
+} hfgpe_params;
+
+/* BAB composition of Eq. prod-gen: B(b_0) A(a_0) B(b_1) ... A(a_{m-1}) B(b_m).
+ * b_0 = 0 gives an ABA-type scheme.  a_i must be non-zero. */
+typedef struct {
+    int m;                 /* number of A stages = FFT pairs per step, 1..16 */
+    const double *a;       /* m stage fractions, sum 1 */
+    const double *b;       /* m+1 B weights, sum 1 */
+    hfgpe_ho_rule ho_rule;
+} hfgpe_scheme;
+
+/* Optional execution settings (zero-initialise for defaults). */
+typedef struct {
+    int steps_per_launch;  /* 1-D: time steps per resident launch (0 = all of
+                              the evolve call up to an internal cap) */
+    int plain;             /* 1 = reference schedule: one launch per step per
+                              grid-size group, no graphs */
+    int use_graph;         /* 1 = replay chunks from a captured hipGraph */
+} hfgpe_options;
+
+typedef struct hfgpe_plan hfgpe_plan;
+
+/* Create a plan for n_inst independent instances (n_inst >= 0; 0 gives an
+ * empty plan whose calls do nothing).  grids and params are host arrays of
+ * n_inst entries, copied into the plan.  All instances share the scheme, the
+ * dtype, the step dt (may be negative) and the spatial dimension.
+ * opts may be NULL.  hip_stream is a hipStream_t or NULL.
+ * Errors: INVALID_ARG, UNSUPPORTED_SHAPE, SINGULAR (a stage |a_i dt| at or
+ * beyond the first zero of g for the largest frequency the instance reaches),
+ * NONPOSITIVE_FREQ, ALLOC, HIP, NO_DEVICE.  On error *out is NULL. */
+int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids,
+                      const hfgpe_params *params, const hfgpe_scheme *scheme,
+                      hfgpe_dtype dtype, double dt, const hfgpe_options *opts,
+                      void *hip_stream);
+
+/* Release a plan and its device workspace (NULL is accepted). */
+int hfgpe_plan_destroy(hfgpe_plan *plan);
+
+/* off[0..n_inst]: start of each instance in the packed buffer, in complex
+ * elements; off[n_inst] is the total the caller must allocate. */
+int hfgpe_instance_offsets(const hfgpe_plan *plan, int64_t *off);
+
+/* Advance every instance nsteps steps of size dt from time t0, in place on
+ * the device buffer d_psi (layout above).  Stream-ordered and asynchronous:
+ * the call returns once the work is enqueued.  On return of the enqueued
+ * work d_psi holds the state at t0 + nsteps*dt with no pending merged phase.
+ * nsteps = 0 does nothing. */
+int hfgpe_evolve(hfgpe_plan *plan, void *d_psi, double t0, int64_t nsteps);
+
+/* Discrete squared norm h^d sum |u|^2 of every instance into the host array
+ * h_out[n_inst] (FP64, compensated summation).  Synchronises the stream. */
+int hfgpe_norm(hfgpe_plan *plan, const void *d_psi, double *h_out);
+
+/* GPE energy of every instance at time t into h_out[4*n_inst]:
+ * (total, kinetic, potential, interaction) per instance, with
+ *   kinetic     = h^d / N sum_k |k|^2 / (2 mu) |u^_k|^2,
+ *   potential   = h^d sum_x (sum_j mu omega_j(t)^2 x_j^2/2 + eps V_I) |u|^2,
+ *   interaction = h^d sum_x sigma(t)/2 |u|^4.
+ * Synchronises the stream. */
+int hfgpe_energy(hfgpe_plan *plan, const void *d_psi, double t, double *h_out);
+
+/* Testing hook: (f, g, e) of every stage and axis of the step starting at tn
+ * for instance inst, computed by the library's closed forms, into
+ * out[(i*ndim + j)*3 + {0,1,2}].  Host only. */
+int hfgpe_stage_coeffs(const hfgpe_plan *plan, int inst, double tn, double *out);
+
+/* Host-only variant of hfgpe_stage_coeffs that needs no plan and no device:
+ * (f, g, e) for one instance described by params (ndim axes) under the scheme
+ * with step dt, for the step starting at tn; same layout as above.  Returns
+ * SINGULAR / NONPOSITIVE_FREQ when a stage is outside the closed forms'
+ * domain. */
+int hfgpe_stage_coeffs_params(const hfgpe_params *params, int ndim, const hfgpe_scheme *scheme,
+                              double dt, double tn, double *out);
+
+/* Named compositions: "leapfrog" (Eq. LeapFrogB), "lie", "srkn6_4",
+ * "ni4_82", "ni5_84" (Table tab.1).  Writes m into *m and, when a and b are
+ * non-NULL, the coefficients (room for 16 and 17 doubles). */
+int hfgpe_scheme_preset(const char *name, int *m, double *a, double *b);
+
+/* Device-side error word raised by the coefficient kernel since the last
+ * call (0 or a status code); synchronises and clears it. */
+int hfgpe_device_status(hfgpe_plan *plan);
+
+const char *hfgpe_status_string(int status);
+int hfgpe_version(int *major, int *minor);
+/* The hipError_t of the last failing HIP call made by the library. */
+int hfgpe_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFGPE_H */

@@ -1,0 +1,232 @@
+"""MI355X Hermite-Fourier GPE time stepping: Python binding of libhfgpe.so.
+
+Thin ctypes binding of the C ABI declared in ``include/hfgpe.h``: argument
+marshalling only.  Every step of the method runs in the library's gfx950 HIP
+kernels; PyTorch provides device memory and the stream.  There is no CPU
+fallback: if the shared library is missing or no gfx950 device is present the
+calls raise.
+
+Method: P. Bader and S. Blanes, "Fourier methods for the perturbed harmonic
+oscillator in linear and nonlinear Schroedinger equations", arXiv:1007.3470.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhfgpe.so")
+
+HFGPE_C64, HFGPE_C128 = 0, 1
+HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2}
+STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "singular stage",
+          -4: "non-positive frequency", -5: "allocation failed", -6: "HIP error",
+          -7: "non-finite coefficient", -8: "no gfx950 device"}
+SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", "hfgpe_evolve",
+           "hfgpe_norm", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
+           "hfgpe_scheme_preset",
+           "hfgpe_device_status", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
+
+
+class HfgpeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (where, STATUS.get(code, "?"), code))
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3)]
+
+
+class SinMod(ctypes.Structure):
+    _fields_ = [("v0", ctypes.c_double), ("amp", ctypes.c_double), ("freq", ctypes.c_double),
+                ("phase", ctypes.c_double)]
+
+
+class VFactor(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("c0", "c2", "c4", "gs", "k", "phi")]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("omega", SinMod * 3), ("sigma", SinMod),
+                ("eps", ctypes.c_double), ("v", VFactor * 3)]
+
+
+class Scheme(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int), ("a", ctypes.POINTER(ctypes.c_double)),
+                ("b", ctypes.POINTER(ctypes.c_double)), ("ho_rule", ctypes.c_int)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("steps_per_launch", ctypes.c_int), ("plain", ctypes.c_int),
+                ("use_graph", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libhfgpe.so (built by ``__graft_entry__.build()``); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhfgpe.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, dp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
+    lib.hfgpe_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(Grid),
+                                      ctypes.POINTER(Params), ctypes.POINTER(Scheme), ctypes.c_int,
+                                      ctypes.c_double, ctypes.POINTER(Options), vp]
+    lib.hfgpe_plan_destroy.argtypes = [vp]
+    lib.hfgpe_instance_offsets.argtypes = [vp, i64p]
+    lib.hfgpe_evolve.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64]
+    lib.hfgpe_norm.argtypes = [vp, vp, dp]
+    lib.hfgpe_energy.argtypes = [vp, vp, ctypes.c_double, dp]
+    lib.hfgpe_stage_coeffs.argtypes = [vp, ctypes.c_int, ctypes.c_double, dp]
+    lib.hfgpe_stage_coeffs_params.argtypes = [ctypes.POINTER(Params), ctypes.c_int,
+                                              ctypes.POINTER(Scheme), ctypes.c_double,
+                                              ctypes.c_double, dp]
+    lib.hfgpe_scheme_preset.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), dp, dp]
+    lib.hfgpe_device_status.argtypes = [vp]
+    lib.hfgpe_status_string.argtypes = [ctypes.c_int]
+    lib.hfgpe_status_string.restype = ctypes.c_char_p
+    lib.hfgpe_version.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != 0:
+        raise HfgpeError(rc, where)
+
+
+def scheme_preset(name: str):
+    """(a, b) of a named composition as held by the library."""
+    lib = load()
+    m = ctypes.c_int(0)
+    a = (ctypes.c_double * 16)()
+    b = (ctypes.c_double * 17)()
+    _check(lib.hfgpe_scheme_preset(name.encode(), ctypes.byref(m), a, b), "hfgpe_scheme_preset")
+    return list(a[: m.value]), list(b[: m.value + 1])
+
+
+def stage_coeffs_params(inst, scheme: str, ho_rule: str, dt: float, tn: float) -> np.ndarray:
+    """(f, g, e) per stage and axis by the library's closed forms (host only)."""
+    lib = load()
+    a, b = scheme_preset(scheme)
+    ca, cb = (ctypes.c_double * len(a))(*a), (ctypes.c_double * len(b))(*b)
+    sch = Scheme(len(a), ca, cb, HO_RULES[ho_rule])
+    out = (ctypes.c_double * (len(a) * inst.ndim * 3))()
+    p = make_params(inst)
+    _check(lib.hfgpe_stage_coeffs_params(ctypes.byref(p), inst.ndim, ctypes.byref(sch), float(dt),
+                                         float(tn), out), "hfgpe_stage_coeffs_params")
+    return np.array(out[:]).reshape(len(a), inst.ndim, 3)
+
+
+def make_grid(inst) -> Grid:
+    g = Grid()
+    g.ndim = inst.ndim
+    for j in range(3):
+        g.n[j] = int(inst.n[j])
+        g.lo[j] = float(inst.lo[j])
+        g.hi[j] = float(inst.hi[j])
+    return g
+
+
+def make_params(inst) -> Params:
+    p = Params()
+    p.mu = float(inst.mu)
+    for j in range(3):
+        p.omega[j] = SinMod(*[float(v) for v in inst.omega[j]])
+        p.v[j] = VFactor(*[float(v) for v in inst.vfac[j]])
+    p.sigma = SinMod(*[float(v) for v in inst.sigma])
+    p.eps = float(inst.eps)
+    return p
+
+
+class Plan:
+    """A batch of instances sharing scheme, dtype and step (hfgpe_plan)."""
+
+    def __init__(self, instances: Sequence, scheme: str = "leapfrog", ho_rule: str = "cf4",
+                 dtype: str = "c128", dt: float = 1e-3, steps_per_launch: int = 0,
+                 plain: bool = False, use_graph: bool = False, stream=None,
+                 a: Optional[Sequence[float]] = None, b: Optional[Sequence[float]] = None):
+        import torch
+        self.lib = load()
+        self.n_inst = len(instances)
+        self.dtype = dtype
+        self.torch_dtype = torch.complex64 if dtype == "c64" else torch.complex128
+        if a is None:
+            a, b = scheme_preset(scheme)
+        self._a = (ctypes.c_double * len(a))(*a)
+        self._b = (ctypes.c_double * len(b))(*b)
+        sch = Scheme(len(a), self._a, self._b, HO_RULES[ho_rule])
+        grids = (Grid * max(1, self.n_inst))(*[make_grid(i) for i in instances])
+        params = (Params * max(1, self.n_inst))(*[make_params(i) for i in instances])
+        opts = Options(int(steps_per_launch), int(bool(plain)), int(bool(use_graph)))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        handle = ctypes.c_void_p()
+        _check(self.lib.hfgpe_plan_create(ctypes.byref(handle), self.n_inst, grids, params,
+                                          ctypes.byref(sch), HFGPE_C64 if dtype == "c64" else HFGPE_C128,
+                                          float(dt), ctypes.byref(opts),
+                                          ctypes.c_void_p(stream.cuda_stream)), "hfgpe_plan_create")
+        self.handle = handle
+        off = (ctypes.c_int64 * (self.n_inst + 1))()
+        _check(self.lib.hfgpe_instance_offsets(self.handle, off), "hfgpe_instance_offsets")
+        self.offsets = np.array(off[:], dtype=np.int64)
+        self.shapes = [tuple(reversed(i.n[: i.ndim])) for i in instances]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.hfgpe_plan_destroy(h)
+            self.handle = None
+
+    # -- buffers ----------------------------------------------------------
+    def pack(self, psis: Iterable[np.ndarray]):
+        """Host arrays (one per instance) -> packed device tensor."""
+        import torch
+        flat = np.concatenate([np.asarray(p, dtype=np.complex128).ravel() for p in psis]) \
+            if self.n_inst else np.zeros(0, np.complex128)
+        assert flat.size == self.offsets[-1]
+        return torch.from_numpy(flat).to(self.torch_dtype).to("cuda")
+
+    def unpack(self, buf) -> List[np.ndarray]:
+        host = buf.detach().to("cpu").to(__import__("torch").complex128).numpy()
+        return [host[self.offsets[k]:self.offsets[k + 1]].reshape(self.shapes[k])
+                for k in range(self.n_inst)]
+
+    def _ptr(self, buf) -> ctypes.c_void_p:
+        assert buf.is_cuda and buf.dtype == self.torch_dtype and buf.is_contiguous()
+        assert buf.numel() >= self.offsets[-1]
+        return ctypes.c_void_p(buf.data_ptr())
+
+    # -- the hot path -----------------------------------------------------
+    def evolve(self, buf, t0: float, nsteps: int) -> None:
+        _check(self.lib.hfgpe_evolve(self.handle, self._ptr(buf), float(t0), int(nsteps)),
+               "hfgpe_evolve")
+
+    def norm(self, buf) -> np.ndarray:
+        out = (ctypes.c_double * max(1, self.n_inst))()
+        _check(self.lib.hfgpe_norm(self.handle, self._ptr(buf), out), "hfgpe_norm")
+        return np.array(out[: self.n_inst])
+
+    def energy(self, buf, t: float) -> np.ndarray:
+        out = (ctypes.c_double * max(4, 4 * self.n_inst))()
+        _check(self.lib.hfgpe_energy(self.handle, self._ptr(buf), float(t), out), "hfgpe_energy")
+        return np.array(out[: 4 * self.n_inst]).reshape(self.n_inst, 4)
+
+    def stage_coeffs(self, inst: int, tn: float, m: int, ndim: int) -> np.ndarray:
+        out = (ctypes.c_double * (m * ndim * 3))()
+        _check(self.lib.hfgpe_stage_coeffs(self.handle, int(inst), float(tn), out),
+               "hfgpe_stage_coeffs")
+        return np.array(out[:]).reshape(m, ndim, 3)
+
+    def device_status(self) -> int:
+        return int(self.lib.hfgpe_device_status(self.handle))

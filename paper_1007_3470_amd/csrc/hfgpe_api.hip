@@ -1,0 +1,615 @@
+// hfgpe_api.hip -- host runtime behind the C ABI in include/hfgpe.h: plan
+// validation and layout, the chunked evolve driver, observables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hfgpe.h"
+#include "coeff.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+using namespace hfgpe;
+
+namespace {
+
+thread_local int g_last_hip_error = 0;
+
+// Steps of coefficient records kept on the device per chunk are limited so
+// the table stays below this many bytes.
+constexpr size_t kRecBudgetBytes = size_t(256) << 20;
+constexpr size_t kRecStepsMax = 16384;
+constexpr int kReduceBlocksMax = 64;
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) {                        \
+            g_last_hip_error = (int)e_;                \
+            return HFGPE_E_HIP;                        \
+        }                                              \
+    } while (0)
+
+bool is_pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
+int ilog2(int n)
+{
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+struct Group1D {
+    int P = 0;
+    int logn = -1;  // >= 0 when the group holds a single grid size (plain mode)
+    std::vector<Item1D> items;
+    Item1D *d_items = nullptr;
+};
+
+}  // namespace
+
+struct hfgpe_plan {
+    int n_inst = 0;
+    int ndim = 1;
+    hfgpe_dtype dtype = HFGPE_C128;
+    double dt = 0.0;
+    hfgpe_options opts{};
+    hipStream_t stream = nullptr;
+    SchemeDev scheme{};
+    std::vector<InstDev> insts;
+    std::vector<int64_t> offsets;
+    std::vector<int> perm;
+    std::vector<Group1D> groups;
+
+    InstDev *d_insts = nullptr;
+    SchemeDev *d_scheme = nullptr;
+    int *d_perm = nullptr;
+    int *d_err = nullptr;
+    Rec *d_rec = nullptr;
+    Rec *d_rec_open = nullptr;
+    int rec_steps_cap = 0;
+    double *d_part = nullptr;
+    double *d_kin = nullptr;
+    int nblk = 1;
+
+    ~hfgpe_plan()
+    {
+        for (auto &g : groups)
+            if (g.d_items) (void)hipFree(g.d_items);
+        if (d_insts) (void)hipFree(d_insts);
+        if (d_scheme) (void)hipFree(d_scheme);
+        if (d_perm) (void)hipFree(d_perm);
+        if (d_err) (void)hipFree(d_err);
+        if (d_rec) (void)hipFree(d_rec);
+        if (d_rec_open) (void)hipFree(d_rec_open);
+        if (d_part) (void)hipFree(d_part);
+        if (d_kin) (void)hipFree(d_kin);
+    }
+};
+
+namespace {
+
+SinMod to_sm(const hfgpe_sinmod &s) { return SinMod{s.v0, s.amp, s.freq, s.phase}; }
+
+// Conservative host-side validity check of every stage for the frequency
+// range an instance can reach, then a sampled check of the exact closed
+// forms over one modulation period.
+int validate_instance(const hfgpe_params &p, int nd, const SchemeDev &S, double dt)
+{
+    if (!(p.mu > 0.0) || !std::isfinite(p.mu)) return HFGPE_E_INVALID_ARG;
+    if (!std::isfinite(p.eps)) return HFGPE_E_INVALID_ARG;
+    const hfgpe_sinmod *sm[4] = {&p.omega[0], &p.omega[1], &p.omega[2], &p.sigma};
+    for (int j = 0; j < 4; ++j) {
+        const hfgpe_sinmod &s = *sm[j];
+        if (!std::isfinite(s.v0) || !std::isfinite(s.amp) || !std::isfinite(s.freq) || !std::isfinite(s.phase))
+            return HFGPE_E_INVALID_ARG;
+    }
+    for (int j = 0; j < 3; ++j) {
+        const hfgpe_vfactor &v = p.v[j];
+        if (!std::isfinite(v.c0) || !std::isfinite(v.c2) || !std::isfinite(v.c4) || !std::isfinite(v.gs) ||
+            !std::isfinite(v.k) || !std::isfinite(v.phi))
+            return HFGPE_E_INVALID_ARG;
+    }
+    double amax = 0.0;
+    for (int i = 0; i < S.m; ++i) amax = std::max(amax, std::fabs(S.a[i]));
+    for (int j = 0; j < nd; ++j) {
+        const hfgpe_sinmod &w = p.omega[j];
+        double wmin = w.v0 * (1.0 - std::fabs(w.amp)), wmax = w.v0 * (1.0 + std::fabs(w.amp));
+        if (!(w.v0 > 0.0) || !(wmin > 0.0)) return HFGPE_E_NONPOSITIVE_FREQ;
+        if (S.rule == HFGPE_HO_EXACT_CONST) {
+            if (w.amp != 0.0) return HFGPE_E_INVALID_ARG;
+            if (!(w.v0 * amax * std::fabs(dt) < M_PI)) return HFGPE_E_SINGULAR;
+        } else {
+            // alpha w_max^2 + beta w_min^2 > 0 keeps omega_L^2, omega_R^2 > 0
+            const double al = 0.5 - 1.0 / std::sqrt(3.0), be = 1.0 - al;
+            if (S.rule == HFGPE_HO_CF4 && !(al * wmax * wmax + be * wmin * wmin > 0.0))
+                return HFGPE_E_NONPOSITIVE_FREQ;
+            if (!(std::sqrt(be) * wmax * amax * std::fabs(dt) < M_PI)) return HFGPE_E_SINGULAR;
+        }
+        // sampled check of the closed forms over one period of omega(t)
+        double period = (w.freq != 0.0 && w.amp != 0.0) ? 2.0 * M_PI / std::fabs(w.freq) : 0.0;
+        SinMod om = to_sm(w);
+        for (int k = 0; k < 64; ++k) {
+            double t = period * k / 64.0;
+            for (int i = 0; i < S.m; ++i) {
+                Fge q = fge_stage(S.rule, p.mu, om, t, dt * S.a[i]);
+                if (q.status) return q.status;
+                if (!std::isfinite(q.f) || !std::isfinite(q.g) || !std::isfinite(q.e)) return HFGPE_E_NONFINITE;
+            }
+            if (period == 0.0) break;
+        }
+    }
+    return HFGPE_OK;
+}
+
+int build_scheme(const hfgpe_scheme *s, int nd, SchemeDev &S)
+{
+    if (!s || !s->a || !s->b || s->m < 1 || s->m > kMaxStages) return HFGPE_E_INVALID_ARG;
+    if (s->ho_rule < HFGPE_HO_EXACT_CONST || s->ho_rule > HFGPE_HO_MAGNUS6) return HFGPE_E_INVALID_ARG;
+    std::memset(&S, 0, sizeof(S));
+    S.m = s->m;
+    S.rule = (int)s->ho_rule;
+    S.ndim = nd;
+    double c = 0.0;
+    for (int i = 0; i < s->m; ++i) {
+        if (!std::isfinite(s->a[i]) || s->a[i] == 0.0) return HFGPE_E_INVALID_ARG;
+        S.a[i] = s->a[i];
+        S.cum[i] = c;
+        c += s->a[i];
+    }
+    S.cum[s->m] = c;
+    for (int i = 0; i <= s->m; ++i) {
+        if (!std::isfinite(s->b[i])) return HFGPE_E_INVALID_ARG;
+        S.b[i] = s->b[i];
+    }
+    return HFGPE_OK;
+}
+
+int check_device()
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return HFGPE_E_NO_DEVICE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HFGPE_E_NO_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return HFGPE_E_NO_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return HFGPE_E_NO_DEVICE;
+    return HFGPE_OK;
+}
+
+// Groups of same-size 1-D instances.  Batched: one group per points-per-thread
+// class, items ordered by decreasing grid size.  Plain: one group per size.
+void build_groups_1d(hfgpe_plan &P, bool plain)
+{
+    std::vector<int> order(P.n_inst);
+    for (int i = 0; i < P.n_inst; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return P.insts[a].n[0] > P.insts[b].n[0]; });
+    P.perm = order;
+    P.groups.clear();
+    int i = 0;
+    while (i < P.n_inst) {
+        int n = P.insts[order[i]].n[0];
+        int Pp = points_per_thread_1d(n);
+        int T = n / Pp;
+        int G = std::max(1, 256 / T);
+        int j = i;
+        while (j < P.n_inst && P.insts[order[j]].n[0] == n) ++j;
+        Group1D *grp = nullptr;
+        for (auto &g : P.groups)
+            if (g.P == Pp && (!plain || g.logn == ilog2(n))) grp = &g;
+        if (!grp) {
+            P.groups.emplace_back();
+            grp = &P.groups.back();
+            grp->P = Pp;
+            grp->logn = plain ? ilog2(n) : -1;
+        }
+        for (int k = i; k < j; k += G) {
+            Item1D it;
+            it.first = k;
+            it.count = std::min(G, j - k);
+            it.logn = ilog2(n);
+            it.pad_ = 0;
+            grp->items.push_back(it);
+        }
+        i = j;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hfgpe_status_string(int status)
+{
+    switch (status) {
+    case HFGPE_OK: return "ok";
+    case HFGPE_E_INVALID_ARG: return "invalid argument";
+    case HFGPE_E_UNSUPPORTED_SHAPE: return "unsupported grid shape";
+    case HFGPE_E_SINGULAR: return "stage reaches the first zero of g (step too large)";
+    case HFGPE_E_NONPOSITIVE_FREQ: return "non-positive (squared) frequency";
+    case HFGPE_E_ALLOC: return "allocation failed";
+    case HFGPE_E_HIP: return "HIP runtime error";
+    case HFGPE_E_NONFINITE: return "non-finite coefficient";
+    case HFGPE_E_NO_DEVICE: return "no gfx950 device";
+    default: return "unknown status";
+    }
+}
+
+int hfgpe_version(int *major, int *minor)
+{
+    if (major) *major = HFGPE_VERSION_MAJOR;
+    if (minor) *minor = HFGPE_VERSION_MINOR;
+    return HFGPE_OK;
+}
+
+int hfgpe_last_hip_error(void) { return g_last_hip_error; }
+
+int hfgpe_scheme_preset(const char *name, int *m, double *a, double *b)
+{
+    if (!name || !m) return HFGPE_E_INVALID_ARG;
+    std::vector<double> A, B;
+    std::string n(name);
+    if (n == "leapfrog") {
+        A = {1.0};
+        B = {0.5, 0.5};
+    } else if (n == "lie") {
+        A = {1.0};
+        B = {1.0, 0.0};
+    } else if (n == "srkn6_4") {  // Table tab.1, 6-stage 4th-order RKN
+        const double b1 = 0.0829844064174052, b2 = 0.396309801498368, b3 = -0.0390563049223486;
+        const double a1 = 0.245298957184271, a2 = 0.604872665711080;
+        const double a3 = 0.5 - (a1 + a2), b4 = 1.0 - 2.0 * (b1 + b2 + b3);
+        A = {a1, a2, a3, a3, a2, a1};
+        B = {b1, b2, b3, b4, b3, b2, b1};
+    } else if (n == "ni4_82") {  // Table tab.1, (8,2); b2 read as 49/180
+        const double a1 = 0.5 - std::sqrt(3.0 / 28.0), a2 = 0.5 - a1;
+        const double b1 = 0.05, b2 = 49.0 / 180.0, b3 = 1.0 - 2.0 * (b1 + b2);
+        A = {a1, a2, a2, a1};
+        B = {b1, b2, b3, b2, b1};
+    } else if (n == "ni5_84") {  // Table tab.1, (8,4)
+        const double a1 = -0.00758691311877447, a2 = 0.317218277973169, a3 = 1.0 - 2.0 * (a1 + a2);
+        const double b1 = 0.811862738544516, b2 = -0.677480399532169, b3 = 0.5 - (b1 + b2);
+        A = {a1, a2, a3, a2, a1};
+        B = {b1, b2, b3, b3, b2, b1};
+    } else {
+        return HFGPE_E_INVALID_ARG;
+    }
+    *m = (int)A.size();
+    if (a) std::copy(A.begin(), A.end(), a);
+    if (b) std::copy(B.begin(), B.end(), b);
+    return HFGPE_OK;
+}
+
+int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, const hfgpe_params *params,
+                      const hfgpe_scheme *scheme, hfgpe_dtype dtype, double dt, const hfgpe_options *opts,
+                      void *hip_stream)
+{
+    if (!out) return HFGPE_E_INVALID_ARG;
+    *out = nullptr;
+    if (n_inst < 0 || (n_inst > 0 && (!grids || !params))) return HFGPE_E_INVALID_ARG;
+    if (dtype != HFGPE_C64 && dtype != HFGPE_C128) return HFGPE_E_INVALID_ARG;
+    if (!std::isfinite(dt) || dt == 0.0) return HFGPE_E_INVALID_ARG;
+    int nd = (n_inst > 0) ? grids[0].ndim : 1;
+    if (nd < 1 || nd > 3) return HFGPE_E_INVALID_ARG;
+    SchemeDev S;
+    int rc = build_scheme(scheme, nd, S);
+    if (rc) return rc;
+    for (int k = 0; k < n_inst; ++k) {
+        const hfgpe_grid &g = grids[k];
+        if (g.ndim != nd) return HFGPE_E_INVALID_ARG;
+        for (int j = 0; j < 3; ++j) {
+            if (j >= nd) {
+                if (g.n[j] != 1) return HFGPE_E_UNSUPPORTED_SHAPE;
+                continue;
+            }
+            if (!is_pow2(g.n[j])) return HFGPE_E_UNSUPPORTED_SHAPE;
+            if (g.n[j] > (nd == 1 ? HFGPE_MAX_N_1D : HFGPE_MAX_N_ND)) return HFGPE_E_UNSUPPORTED_SHAPE;
+            if (!std::isfinite(g.lo[j]) || !std::isfinite(g.hi[j]) || !(g.hi[j] > g.lo[j]))
+                return HFGPE_E_INVALID_ARG;
+        }
+        rc = validate_instance(params[k], nd, S, dt);
+        if (rc) return rc;
+    }
+    if (nd != 1 && n_inst > 0) return HFGPE_E_UNSUPPORTED_SHAPE;  // d-D kernels: see kern_nd
+    if (n_inst > 0) {
+        rc = check_device();
+        if (rc) return rc;
+    }
+
+    hfgpe_plan *P = new (std::nothrow) hfgpe_plan();
+    if (!P) return HFGPE_E_ALLOC;
+    P->n_inst = n_inst;
+    P->ndim = nd;
+    P->dtype = dtype;
+    P->dt = dt;
+    if (opts) P->opts = *opts;
+    P->stream = (hipStream_t)hip_stream;
+    P->scheme = S;
+    P->insts.resize(n_inst);
+    P->offsets.resize(n_inst + 1);
+    int64_t off = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const hfgpe_grid &g = grids[k];
+        const hfgpe_params &p = params[k];
+        InstDev &I = P->insts[k];
+        std::memset(&I, 0, sizeof(I));
+        I.offset = off;
+        I.ndim = nd;
+        int64_t pts = 1;
+        for (int j = 0; j < 3; ++j) {
+            I.n[j] = (j < nd) ? g.n[j] : 1;
+            I.logn[j] = ilog2(I.n[j]);
+            I.lo[j] = (j < nd) ? g.lo[j] : 0.0;
+            double L = (j < nd) ? (g.hi[j] - g.lo[j]) : 1.0;
+            I.dx[j] = L / (double)I.n[j];
+            I.kscale[j] = 2.0 * M_PI / L;
+            I.om[j] = to_sm(p.omega[j]);
+            I.vf[j] = VFac{p.v[j].c0, p.v[j].c2, p.v[j].c4, p.v[j].gs, p.v[j].k, p.v[j].phi};
+            pts *= I.n[j];
+        }
+        I.mu = p.mu;
+        I.eps = p.eps;
+        I.sig = to_sm(p.sigma);
+        P->offsets[k] = off;
+        off += pts;
+    }
+    P->offsets[n_inst] = off;
+    if (n_inst == 0) {
+        *out = P;
+        return HFGPE_OK;
+    }
+
+    build_groups_1d(*P, P->opts.plain != 0);
+    int64_t maxpts = 0;
+    for (auto &I : P->insts) maxpts = std::max<int64_t>(maxpts, (int64_t)I.n[0] * I.n[1] * I.n[2]);
+    P->nblk = (int)std::min<int64_t>(kReduceBlocksMax, std::max<int64_t>(1, (maxpts + 4095) / 4096));
+    size_t per_step = (size_t)n_inst * S.m * sizeof(Rec);
+    P->rec_steps_cap = (int)std::max<size_t>(1, std::min<size_t>(kRecBudgetBytes / per_step, kRecStepsMax));
+
+#define ALLOC_TRY(ptr, bytes)                                      \
+    do {                                                           \
+        hipError_t e_ = hipMalloc((void **)&(ptr), (bytes));      \
+        if (e_ != hipSuccess) {                                    \
+            g_last_hip_error = (int)e_;                            \
+            delete P;                                              \
+            return HFGPE_E_ALLOC;                                  \
+        }                                                          \
+    } while (0)
+#define COPY_TRY(dst, src, bytes)                                                      \
+    do {                                                                               \
+        hipError_t e_ = hipMemcpy((dst), (src), (bytes), hipMemcpyHostToDevice);       \
+        if (e_ != hipSuccess) {                                                        \
+            g_last_hip_error = (int)e_;                                                \
+            delete P;                                                                  \
+            return HFGPE_E_HIP;                                                        \
+        }                                                                              \
+    } while (0)
+
+    ALLOC_TRY(P->d_insts, sizeof(InstDev) * n_inst);
+    COPY_TRY(P->d_insts, P->insts.data(), sizeof(InstDev) * n_inst);
+    ALLOC_TRY(P->d_scheme, sizeof(SchemeDev));
+    COPY_TRY(P->d_scheme, &P->scheme, sizeof(SchemeDev));
+    ALLOC_TRY(P->d_perm, sizeof(int) * n_inst);
+    COPY_TRY(P->d_perm, P->perm.data(), sizeof(int) * n_inst);
+    ALLOC_TRY(P->d_err, sizeof(int));
+    {
+        int z = 0;
+        COPY_TRY(P->d_err, &z, sizeof(int));
+    }
+    ALLOC_TRY(P->d_rec_open, sizeof(Rec) * n_inst);
+    ALLOC_TRY(P->d_rec, sizeof(Rec) * (size_t)n_inst * S.m * P->rec_steps_cap);
+    ALLOC_TRY(P->d_part, sizeof(double) * 4 * (size_t)n_inst * P->nblk);
+    ALLOC_TRY(P->d_kin, sizeof(double) * n_inst);
+    for (auto &g : P->groups) {
+        ALLOC_TRY(g.d_items, sizeof(Item1D) * g.items.size());
+        COPY_TRY(g.d_items, g.items.data(), sizeof(Item1D) * g.items.size());
+    }
+#undef ALLOC_TRY
+#undef COPY_TRY
+    *out = P;
+    return HFGPE_OK;
+}
+
+int hfgpe_plan_destroy(hfgpe_plan *plan)
+{
+    delete plan;
+    return HFGPE_OK;
+}
+
+int hfgpe_instance_offsets(const hfgpe_plan *plan, int64_t *off)
+{
+    if (!plan || !off) return HFGPE_E_INVALID_ARG;
+    std::copy(plan->offsets.begin(), plan->offsets.end(), off);
+    return HFGPE_OK;
+}
+
+int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
+{
+    if (!P || nsteps < 0 || !std::isfinite(t0)) return HFGPE_E_INVALID_ARG;
+    if (nsteps == 0 || P->n_inst == 0) return HFGPE_OK;
+    if (!d_psi) return HFGPE_E_INVALID_ARG;
+    const int m = P->scheme.m;
+    int chunk = (int)std::min<int64_t>(nsteps, P->rec_steps_cap);
+    const bool plain = P->opts.plain != 0;
+    int per_launch = plain ? 1 : (P->opts.steps_per_launch > 0 ? P->opts.steps_per_launch : chunk);
+    for (int64_t s0 = 0; s0 < nsteps; s0 += chunk) {
+        int k = (int)std::min<int64_t>(chunk, nsteps - s0);
+        LaunchCoeff C;
+        C.insts = P->d_insts;
+        C.n_inst = P->n_inst;
+        C.scheme = P->d_scheme;
+        C.rec = P->d_rec;
+        C.rec_open = P->d_rec_open;
+        C.t0 = t0;
+        C.dt = P->dt;
+        C.step0 = s0;
+        C.k_steps = k;
+        C.nsteps_total = nsteps;
+        C.err = P->d_err;
+        C.stream = P->stream;
+        HIP_TRY(launch_coeff(C));
+        for (int sb = 0; sb < k; sb += per_launch) {
+            int kk = std::min(per_launch, k - sb);
+            for (auto &g : P->groups) {
+                Launch1D L;
+                L.items = g.d_items;
+                L.n_items = (int)g.items.size();
+                L.P = g.P;
+                L.perm = P->d_perm;
+                L.insts = P->d_insts;
+                L.rec = P->d_rec;
+                L.rec_open = P->d_rec_open;
+                L.psi = d_psi;
+                L.m = m;
+                L.K = kk;
+                L.rec_steps = k;
+                L.step_base = sb;
+                L.apply_opening = (s0 == 0 && sb == 0) ? 1 : 0;
+                L.c64 = P->dtype == HFGPE_C64;
+                L.stream = P->stream;
+                HIP_TRY(launch_hf1d(L));
+            }
+        }
+    }
+    return HFGPE_OK;
+}
+
+static double ksum(const double *v, int n, int stride)
+{
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double x = v[(size_t)i * stride];
+        double t = s + x;
+        c += (std::fabs(s) >= std::fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+    return s + c;
+}
+
+static int run_reduce(hfgpe_plan *P, const void *d_psi, int energy, double t, std::vector<double> &part)
+{
+    LaunchReduce R;
+    R.insts = P->d_insts;
+    R.n_inst = P->n_inst;
+    R.nblk = P->nblk;
+    R.psi = d_psi;
+    R.c64 = P->dtype == HFGPE_C64;
+    R.energy = energy;
+    R.t = t;
+    R.part = P->d_part;
+    R.stream = P->stream;
+    HIP_TRY(launch_reduce_pointwise(R));
+    part.resize((size_t)4 * P->n_inst * P->nblk);
+    HIP_TRY(hipMemcpyAsync(part.data(), P->d_part, sizeof(double) * part.size(), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    return HFGPE_OK;
+}
+
+int hfgpe_norm(hfgpe_plan *P, const void *d_psi, double *h_out)
+{
+    if (!P || (!h_out && P->n_inst > 0)) return HFGPE_E_INVALID_ARG;
+    if (P->n_inst == 0) return HFGPE_OK;
+    if (!d_psi) return HFGPE_E_INVALID_ARG;
+    std::vector<double> part;
+    int rc = run_reduce(P, d_psi, 0, 0.0, part);
+    if (rc) return rc;
+    for (int k = 0; k < P->n_inst; ++k) {
+        const InstDev &I = P->insts[k];
+        double cell = I.dx[0] * (I.ndim > 1 ? I.dx[1] : 1.0) * (I.ndim > 2 ? I.dx[2] : 1.0);
+        h_out[k] = cell * ksum(&part[(size_t)k * P->nblk * 4], P->nblk, 4);
+    }
+    return HFGPE_OK;
+}
+
+int hfgpe_energy(hfgpe_plan *P, const void *d_psi, double t, double *h_out)
+{
+    if (!P || (!h_out && P->n_inst > 0) || !std::isfinite(t)) return HFGPE_E_INVALID_ARG;
+    if (P->n_inst == 0) return HFGPE_OK;
+    if (!d_psi) return HFGPE_E_INVALID_ARG;
+    for (auto &g : P->groups) {
+        LaunchKin1D K;
+        K.items = g.d_items;
+        K.n_items = (int)g.items.size();
+        K.P = g.P;
+        K.perm = P->d_perm;
+        K.insts = P->d_insts;
+        K.psi = d_psi;
+        K.c64 = P->dtype == HFGPE_C64;
+        K.kin = P->d_kin;
+        K.stream = P->stream;
+        HIP_TRY(launch_kinetic_1d(K));
+    }
+    std::vector<double> kin(P->n_inst);
+    HIP_TRY(hipMemcpyAsync(kin.data(), P->d_kin, sizeof(double) * P->n_inst, hipMemcpyDeviceToHost, P->stream));
+    std::vector<double> part;
+    int rc = run_reduce(P, d_psi, 1, t, part);
+    if (rc) return rc;
+    for (int k = 0; k < P->n_inst; ++k) {
+        const InstDev &I = P->insts[k];
+        double cell = I.dx[0] * (I.ndim > 1 ? I.dx[1] : 1.0) * (I.ndim > 2 ? I.dx[2] : 1.0);
+        double ek = cell * kin[k];
+        double ep = cell * ksum(&part[(size_t)k * P->nblk * 4 + 1], P->nblk, 4);
+        double ei = cell * ksum(&part[(size_t)k * P->nblk * 4 + 2], P->nblk, 4);
+        h_out[4 * k + 0] = ek + ep + ei;
+        h_out[4 * k + 1] = ek;
+        h_out[4 * k + 2] = ep;
+        h_out[4 * k + 3] = ei;
+    }
+    return HFGPE_OK;
+}
+
+int hfgpe_stage_coeffs(const hfgpe_plan *P, int inst, double tn, double *out)
+{
+    if (!P || !out || inst < 0 || inst >= P->n_inst || !std::isfinite(tn)) return HFGPE_E_INVALID_ARG;
+    const InstDev &I = P->insts[inst];
+    const SchemeDev &S = P->scheme;
+    for (int i = 0; i < S.m; ++i) {
+        double tau = tn + P->dt * S.cum[i];
+        for (int j = 0; j < I.ndim; ++j) {
+            Fge q = fge_stage(S.rule, I.mu, I.om[j], tau, P->dt * S.a[i]);
+            if (q.status) return q.status;
+            out[(i * I.ndim + j) * 3 + 0] = q.f;
+            out[(i * I.ndim + j) * 3 + 1] = q.g;
+            out[(i * I.ndim + j) * 3 + 2] = q.e;
+        }
+    }
+    return HFGPE_OK;
+}
+
+int hfgpe_stage_coeffs_params(const hfgpe_params *params, int ndim, const hfgpe_scheme *scheme, double dt,
+                              double tn, double *out)
+{
+    if (!params || !out || ndim < 1 || ndim > 3 || !std::isfinite(tn) || !std::isfinite(dt)) return HFGPE_E_INVALID_ARG;
+    SchemeDev S;
+    int rc = build_scheme(scheme, ndim, S);
+    if (rc) return rc;
+    for (int i = 0; i < S.m; ++i) {
+        double tau = tn + dt * S.cum[i];
+        for (int j = 0; j < ndim; ++j) {
+            Fge q = fge_stage(S.rule, params->mu, to_sm(params->omega[j]), tau, dt * S.a[i]);
+            if (q.status) return q.status;
+            out[(i * ndim + j) * 3 + 0] = q.f;
+            out[(i * ndim + j) * 3 + 1] = q.g;
+            out[(i * ndim + j) * 3 + 2] = q.e;
+        }
+    }
+    return HFGPE_OK;
+}
+
+int hfgpe_device_status(hfgpe_plan *P)
+{
+    if (!P) return HFGPE_E_INVALID_ARG;
+    if (P->n_inst == 0) return HFGPE_OK;
+    int v = 0, z = 0;
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    HIP_TRY(hipMemcpy(&v, P->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(P->d_err, &z, sizeof(int), hipMemcpyHostToDevice));
+    return v;
+}
+
+}  // extern "C"

@@ -1,0 +1,352 @@
+// kern_1d.hip -- resident 1-D Hermite-Fourier step kernel for gfx950.
+//
+// One workgroup of 256 threads owns `count` same-size instances for K time
+// steps (K up to a whole evolve call): the state is loaded from HBM once, kept
+// in FP64 registers, advanced K steps and stored once.  Per stage (Sec. 3,
+// Eq. leapfrogHF / prod-genHarmOsc):
+//   forward FFT  ->  drift D(g) = exp(-i g k^2/2) (and 1/N)  ->  inverse FFT
+//   ->  merged x-space phase exp(-i (chi x^2/2 + w eps V_I + s |u|^2))
+// The FFT is a Stockham auto-sort FFT split over the T = N/P threads of an
+// instance: every pass is a radix-P butterfly on P registers (the first pass
+// may use a smaller radix), with an LDS exchange between passes.  Thread t
+// holds the points {t + c T, c = 0..P-1} both before the first pass and after
+// the last one, so the drift, the x-phase and the step boundary need no data
+// movement.  Twiddles of passes 1.. are computed once per launch (sincospi of
+// exact dyadic angles) and stay in registers; phases use the FP64 cis_neg.
+// Storage: Store = float2 (c64) or double2 (c128) in HBM; Xch = the LDS
+// exchange type.  Arithmetic is FP64 throughout.
+#include <hip/hip_runtime.h>
+
+#include "coeff.hpp"
+#include "devmath.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace hfgpe {
+
+constexpr int kThreads1D = 256;
+constexpr int kPadShift = 4;  // one padding element every 16 in LDS
+
+__device__ __forceinline__ int lds_pad(int idx) { return idx + (idx >> kPadShift); }
+
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+template <typename T>
+__device__ __forceinline__ T from_d2(double2 v);
+template <>
+__device__ __forceinline__ float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+template <>
+__device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
+
+template <int P>
+struct Log2 {
+    static constexpr int value = (P <= 1) ? 0 : 1 + Log2<P / 2>::value;
+};
+template <>
+struct Log2<1> {
+    static constexpr int value = 0;
+};
+
+template <typename Xch, int P, int MAXS>
+struct Fft1D {
+    static constexpr int LOGP = Log2<P>::value;
+    static constexpr int NTW = (MAXS > 1) ? MAXS - 1 : 1;
+    static constexpr int PW = (P > 1) ? P - 1 : 1;
+
+    int logn, logT, S, r0log, tl;
+    Xch *buf;
+    double2 tw[NTW][PW];
+
+    __device__ void init(int logn_, int tl_, Xch *buf_)
+    {
+        logn = logn_;
+        tl = tl_;
+        buf = buf_;
+        logT = logn - LOGP;
+        S = (logn == 0 || LOGP == 0) ? 0 : (logn + LOGP - 1) / (LOGP > 0 ? LOGP : 1);
+        r0log = (S == 0) ? 0 : logn - LOGP * (S - 1);
+        const double invN = 1.0 / (double)(1 << logn);
+#pragma unroll
+        for (int s = 1; s < MAXS; ++s) {
+            if (s < S) {
+                int logL = r0log + LOGP * (s - 1);
+                int k = tl & ((1 << logL) - 1);
+                int slog = logn - logL - LOGP;
+#pragma unroll
+                for (int r = 1; r < P; ++r) {
+                    int e = (r * k) << slog;
+                    double sn, cs;
+                    sincospi(-2.0 * (double)e * invN, &sn, &cs);
+                    tw[s - 1][r - 1] = make_double2(cs, sn);
+                }
+            }
+        }
+    }
+
+    template <int R, int SGN>
+    __device__ __forceinline__ void pass0(double2 *u)
+    {
+        constexpr int NB = P / R;
+        const int T = 1 << logT;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double2 v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = u[b + r * NB];
+            Dft<R, SGN>::run(v);
+            int j = tl + b * T;
+#pragma unroll
+            for (int rp = 0; rp < R; ++rp) buf[lds_pad(j * R + rp)] = from_d2<Xch>(v[rp]);
+        }
+    }
+
+    template <int SGN>
+    __device__ __forceinline__ void run(double2 *u)
+    {
+        if constexpr (P == 1) {
+            return;
+        } else {
+            if (S == 1) {  // N == P: one thread holds the whole instance
+                Dft<P, SGN>::run(u);
+                return;
+            }
+            switch (r0log) {
+            case 1: pass0<2, SGN>(u); break;
+            case 2: pass0<4, SGN>(u); break;
+            case 3: if constexpr (P >= 8) pass0<8, SGN>(u); break;
+            case 4: if constexpr (P >= 16) pass0<16, SGN>(u); break;
+            default: break;
+            }
+            const int T = 1 << logT;
+#pragma unroll
+            for (int s = 1; s < MAXS; ++s) {
+                if (s < S) {
+                    __syncthreads();
+#pragma unroll
+                    for (int c = 0; c < P; ++c) u[c] = to_d2(buf[lds_pad(tl + c * T)]);
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 1; r < P; ++r)
+                        u[r] = (SGN < 0) ? cmul(u[r], tw[s - 1][r - 1]) : cmulc(u[r], tw[s - 1][r - 1]);
+                    Dft<P, SGN>::run(u);
+                    if (s < S - 1) {
+                        int logL = r0log + LOGP * (s - 1);
+                        int L = 1 << logL;
+                        int k = tl & (L - 1);
+                        int base = (tl - k) * P + k;
+#pragma unroll
+                        for (int rp = 0; rp < P; ++rp) buf[lds_pad(base + rp * L)] = from_d2<Xch>(u[rp]);
+                    }
+                }
+            }
+        }
+    }
+};
+
+template <typename Store, typename Xch, int P, int MAXS>
+__global__ __launch_bounds__(kThreads1D) void hf1d_kernel(const Item1D *__restrict__ items,
+                                                          const int *__restrict__ perm,
+                                                          const InstDev *__restrict__ insts,
+                                                          const Rec *__restrict__ rec,
+                                                          const Rec *__restrict__ rec_open,
+                                                          Store *__restrict__ psi, int m, int K,
+                                                          int rec_steps, int step_base,
+                                                          int apply_opening)
+{
+    constexpr int LOGP = Log2<P>::value;
+    constexpr int LDS_ELEMS = kThreads1D * P + ((kThreads1D * P) >> kPadShift);
+    __shared__ Xch lds[LDS_ELEMS];
+
+    const Item1D it = items[blockIdx.x];
+    const int logn = it.logn;
+    const int N = 1 << logn;
+    const int logT = logn - LOGP;
+    const int T = 1 << logT;
+    const int tid = threadIdx.x;
+    const int slot = tid >> logT;
+    const int tl = tid & (T - 1);
+    const bool active = slot < it.count;
+    const int inst_id = perm[it.first + (active ? slot : 0)];
+    const InstDev &I = insts[inst_id];
+
+    Fft1D<Xch, P, MAXS> fft;
+    fft.init(logn, tl, lds + slot * (N + (N >> kPadShift)));
+
+    double2 u[P];
+    double x2h[P], ve[P];
+    const double lo = I.lo[0], dx = I.dx[0], eps = I.eps;
+    const VFac vf = I.vf[0];
+    Store *base = psi + I.offset;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int i = tl + c * T;
+        double x = lo + (double)i * dx;
+        x2h[c] = 0.5 * x * x;
+        ve[c] = eps * vfactor(vf, x);
+        u[c] = active ? to_d2(base[i]) : make_double2(0.0, 0.0);
+    }
+
+    auto xphase = [&](const Rec &r) {
+        const double chi = r.chi[0], w = r.w, s = r.s;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
+            double th = fma(chi, x2h[c], fma(w, ve[c], s * a2));
+            u[c] = cmul(u[c], cis_neg(th));
+        }
+    };
+
+    const double invN = 1.0 / (double)N;
+    const double ks = I.kscale[0];
+    if (apply_opening) xphase(rec_open[inst_id]);
+    const Rec *rp = rec + ((size_t)inst_id * (size_t)rec_steps + (size_t)step_base) * (size_t)m;
+    for (int step = 0; step < K; ++step) {
+        for (int st = 0; st < m; ++st) {
+            const Rec r = rp[step * m + st];
+            fft.template run<-1>(u);
+            const double g = r.g[0];
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                int q = tl + c * T;
+                int sq = q - ((q >= (N >> 1)) ? N : 0);
+                double k = ks * (double)sq;
+                double2 f = cis_neg(g * (0.5 * k * k));
+                u[c] = cmul(u[c], make_double2(f.x * invN, f.y * invN));
+            }
+            fft.template run<+1>(u);
+            xphase(r);
+        }
+    }
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < P; ++c) base[tl + c * T] = from_d2<Store>(u[c]);
+    }
+}
+
+// Kinetic energy of 1-D instances: sum_k k^2 |u^_k|^2 / (2 mu N), forward FFT
+// in LDS with FP64 exchange, per-thread compensated sums combined in a fixed
+// order by the first thread of each instance slot.
+template <typename Store, int P, int MAXS>
+__global__ __launch_bounds__(kThreads1D) void kin1d_kernel(const Item1D *__restrict__ items,
+                                                           const int *__restrict__ perm,
+                                                           const InstDev *__restrict__ insts,
+                                                           const Store *__restrict__ psi,
+                                                           double *__restrict__ kin)
+{
+    constexpr int LOGP = Log2<P>::value;
+    constexpr int LDS_ELEMS = kThreads1D * P + ((kThreads1D * P) >> kPadShift);
+    __shared__ double2 lds[LDS_ELEMS];
+    __shared__ double part[2][kThreads1D];
+
+    const Item1D it = items[blockIdx.x];
+    const int logn = it.logn;
+    const int N = 1 << logn;
+    const int logT = logn - LOGP;
+    const int T = 1 << logT;
+    const int tid = threadIdx.x;
+    const int slot = tid >> logT;
+    const int tl = tid & (T - 1);
+    const bool active = slot < it.count;
+    const int inst_id = perm[it.first + (active ? slot : 0)];
+    const InstDev &I = insts[inst_id];
+
+    Fft1D<double2, P, MAXS> fft;
+    fft.init(logn, tl, lds + slot * (N + (N >> kPadShift)));
+    double2 u[P];
+    const Store *base = psi + I.offset;
+#pragma unroll
+    for (int c = 0; c < P; ++c) u[c] = active ? to_d2(base[tl + c * T]) : make_double2(0.0, 0.0);
+    fft.template run<-1>(u);
+    double s = 0.0, cc = 0.0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int q = tl + c * T;
+        int sq = q - ((q >= (N >> 1)) ? N : 0);
+        double k = I.kscale[0] * (double)sq;
+        double v = k * k * fma(u[c].x, u[c].x, u[c].y * u[c].y);
+        double t = s + v;
+        cc += (fabs(s) >= fabs(v)) ? ((s - t) + v) : ((v - t) + s);
+        s = t;
+    }
+    part[0][tid] = s;
+    part[1][tid] = cc;
+    __syncthreads();
+    if (active && tl == 0) {
+        double a = 0.0, ac = 0.0;
+        for (int i = 0; i < T; ++i) {
+            double v = part[0][tid + i] + part[1][tid + i];
+            double t = a + v;
+            ac += (fabs(a) >= fabs(v)) ? ((a - t) + v) : ((v - t) + a);
+            a = t;
+        }
+        kin[inst_id] = (a + ac) / (2.0 * I.mu * (double)N);
+    }
+}
+
+template <typename Store, int P, int MAXS>
+static hipError_t launch_kin_p(const LaunchKin1D &L)
+{
+    hipLaunchKernelGGL((kin1d_kernel<Store, P, MAXS>), dim3(L.n_items), dim3(kThreads1D), 0, L.stream,
+                       L.items, L.perm, L.insts, (const Store *)L.psi, L.kin);
+    return hipGetLastError();
+}
+
+template <typename Store>
+static hipError_t launch_kin_store(const LaunchKin1D &L)
+{
+    switch (L.P) {
+    case 1: return launch_kin_p<Store, 1, 1>(L);
+    case 2: return launch_kin_p<Store, 2, 1>(L);
+    case 4: return launch_kin_p<Store, 4, 1>(L);
+    case 8: return launch_kin_p<Store, 8, 4>(L);
+    case 16: return launch_kin_p<Store, 16, 3>(L);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_kinetic_1d(const LaunchKin1D &L)
+{
+    if (L.n_items <= 0) return hipSuccess;
+    if (L.c64) return launch_kin_store<float2>(L);
+    return launch_kin_store<double2>(L);
+}
+
+template <typename Store, typename Xch, int P, int MAXS>
+static hipError_t launch_p(const Launch1D &L)
+{
+    hipLaunchKernelGGL((hf1d_kernel<Store, Xch, P, MAXS>), dim3(L.n_items), dim3(kThreads1D), 0, L.stream,
+                       L.items, L.perm, L.insts, L.rec, L.rec_open, (Store *)L.psi, L.m, L.K, L.rec_steps,
+                       L.step_base, L.apply_opening);
+    return hipGetLastError();
+}
+
+template <typename Store, typename Xch>
+static hipError_t launch_store(const Launch1D &L)
+{
+    switch (L.P) {
+    case 1: return launch_p<Store, Xch, 1, 1>(L);
+    case 2: return launch_p<Store, Xch, 2, 1>(L);
+    case 4: return launch_p<Store, Xch, 4, 1>(L);
+    case 8: return launch_p<Store, Xch, 8, 4>(L);
+    case 16: return launch_p<Store, Xch, 16, 3>(L);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_hf1d(const Launch1D &L)
+{
+    if (L.n_items <= 0) return hipSuccess;
+    if (L.c64) return launch_store<float2, float2>(L);
+    return launch_store<double2, double2>(L);
+}
+
+int points_per_thread_1d(int n)
+{
+    if (n <= 1) return 1;
+    if (n <= 4) return n;
+    if (n <= 2048) return 8;
+    if (n == 4096) return 16;
+    return 0;
+}
+
+}  // namespace hfgpe

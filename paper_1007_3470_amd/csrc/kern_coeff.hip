@@ -1,0 +1,110 @@
+// kern_coeff.hip -- per (instance, step) stage-coefficient kernel.
+//
+// For every instance and every step n of a chunk it evaluates, in FP64, the
+// harmonic-oscillator coefficients (f, g, e) of each stage i over
+// [tau_i, tau_i + a_i dt] with tau_i = t_n + dt (a_0 + ... + a_{i-1}) (time
+// frozen in B as in Table "algorithm"), and writes one record per stage: the
+// stage's drift coefficient g_i and the x-space phase applied after it, in
+// which adjacent chirps and B flows are merged (Eq. leapfrogHF,
+// Eq. prod-genHarmOsc):
+//   inside a step:         chi = f_i + e_{i+1},      w = dt b_{i+1} at tau_{i+1}
+//   across a step boundary: chi = f_{m-1} + e'_0,     w = dt (b_m + b_0) at t_{n+1}
+//   after the last step:    chi = f_{m-1},            w = dt b_m at t_{n+1}
+// and s = w sigma(tau).  The opening phase of an evolve call
+// (chi = e_0(t_0), w = dt b_0 at t_0) goes to rec_open.
+#include <hip/hip_runtime.h>
+
+#include "coeff.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace hfgpe {
+
+__device__ __forceinline__ void raise_err(int *err, int code)
+{
+    if (code != 0) atomicCAS(err, 0, code);
+}
+
+__global__ void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
+                             const SchemeDev *__restrict__ sch, Rec *__restrict__ rec,
+                             Rec *__restrict__ rec_open, double t0, double dt, int64_t step0,
+                             int k_steps, int64_t nsteps_total, int *err)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n_inst * k_steps) return;
+    const int inst = (int)(idx / k_steps);
+    const int s = (int)(idx % k_steps);
+    const InstDev &I = insts[inst];
+    const int m = sch->m, rule = sch->rule, nd = I.ndim;
+    const int64_t n = step0 + s;
+    const double tn = t0 + (double)n * dt;
+    const double tn1 = t0 + (double)(n + 1) * dt;
+    const bool last = (n == nsteps_total - 1);
+
+    double fprev[3];
+    Rec *out = rec + ((size_t)inst * k_steps + s) * m;
+    Fge cur[3];
+    for (int j = 0; j < nd; ++j) {
+        cur[j] = fge_stage(rule, I.mu, I.om[j], tn, dt * sch->a[0]);
+        raise_err(err, cur[j].status);
+    }
+    if (n == 0) {
+        Rec o;
+        for (int j = 0; j < 3; ++j) {
+            o.g[j] = 0.0;
+            o.chi[j] = (j < nd) ? cur[j].e : 0.0;
+        }
+        o.w = dt * sch->b[0];
+        o.s = o.w * sinmod(I.sig, tn);
+        rec_open[inst] = o;
+    }
+    for (int i = 0; i < m; ++i) {
+        Rec r;
+        for (int j = 0; j < 3; ++j) { r.g[j] = 0.0; r.chi[j] = 0.0; }
+        for (int j = 0; j < nd; ++j) {
+            r.g[j] = cur[j].g;
+            fprev[j] = cur[j].f;
+        }
+        double tau_next;
+        if (i < m - 1) {
+            tau_next = tn + dt * sch->cum[i + 1];
+            for (int j = 0; j < nd; ++j) {
+                cur[j] = fge_stage(rule, I.mu, I.om[j], tau_next, dt * sch->a[i + 1]);
+                raise_err(err, cur[j].status);
+                r.chi[j] = fprev[j] + cur[j].e;
+            }
+            r.w = dt * sch->b[i + 1];
+        } else if (!last) {
+            tau_next = tn1;
+            for (int j = 0; j < nd; ++j) {
+                Fge q = fge_stage(rule, I.mu, I.om[j], tn1, dt * sch->a[0]);
+                raise_err(err, q.status);
+                r.chi[j] = fprev[j] + q.e;
+            }
+            r.w = dt * (sch->b[m] + sch->b[0]);
+        } else {
+            tau_next = tn1;
+            for (int j = 0; j < nd; ++j) r.chi[j] = fprev[j];
+            r.w = dt * sch->b[m];
+        }
+        r.s = r.w * sinmod(I.sig, tau_next);
+        bool finite = isfinite(r.w) && isfinite(r.s);
+        for (int j = 0; j < 3; ++j) finite = finite && isfinite(r.g[j]) && isfinite(r.chi[j]);
+        if (!finite) raise_err(err, -7);
+        out[i] = r;
+    }
+}
+
+hipError_t launch_coeff(const LaunchCoeff &L)
+{
+    int64_t total = (int64_t)L.n_inst * L.k_steps;
+    if (total <= 0) return hipSuccess;
+    const int bs = 128;
+    int64_t grid = (total + bs - 1) / bs;
+    hipLaunchKernelGGL(coeff_kernel, dim3((unsigned)grid), dim3(bs), 0, L.stream, L.insts, L.n_inst,
+                       L.scheme, L.rec, L.rec_open, L.t0, L.dt, L.step0, L.k_steps, L.nsteps_total,
+                       L.err);
+    return hipGetLastError();
+}
+
+}  // namespace hfgpe

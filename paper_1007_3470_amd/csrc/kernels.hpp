@@ -1,0 +1,78 @@
+// kernels.hpp -- host-side launchers of the gfx950 kernels (one per .hip file).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace hfgpe {
+
+// ---- coefficient kernel (kern_coeff.hip) ---------------------------------
+struct LaunchCoeff {
+    const InstDev *insts;
+    int n_inst;
+    const SchemeDev *scheme;  // device copy
+    Rec *rec;                 // [n_inst][k_steps][m]
+    Rec *rec_open;            // [n_inst]
+    double t0, dt;
+    int64_t step0;            // global index of the chunk's first step
+    int k_steps;              // steps in this chunk
+    int64_t nsteps_total;     // steps of the whole evolve call
+    int *err;                 // device error word
+    hipStream_t stream;
+};
+hipError_t launch_coeff(const LaunchCoeff &L);
+
+// ---- 1-D resident step kernel (kern_1d.hip) ------------------------------
+struct Launch1D {
+    const Item1D *items;
+    int n_items;
+    int P;  // points per thread of this item group
+    const int *perm;
+    const InstDev *insts;
+    const Rec *rec;
+    const Rec *rec_open;
+    void *psi;
+    int m;
+    int K;            // steps advanced by this launch
+    int rec_steps;    // steps per instance held in rec (row stride)
+    int step_base;    // first step of this launch within rec
+    int apply_opening;
+    int c64;
+    hipStream_t stream;
+};
+hipError_t launch_hf1d(const Launch1D &L);
+int points_per_thread_1d(int n);
+
+// ---- observables (kern_reduce.hip) ----------------------------------------
+// Per-instance partial sums written to part[(inst * nblk + blk) * 4 + q] as
+// (sum |u|^2, sum V |u|^2, sum sigma/2 |u|^4, unused).
+struct LaunchReduce {
+    const InstDev *insts;
+    int n_inst;
+    int nblk;          // blocks per instance
+    const void *psi;
+    int c64;
+    int energy;        // 0: only |u|^2
+    double t;          // time for omega(t), sigma(t)
+    double *part;
+    hipStream_t stream;
+};
+hipError_t launch_reduce_pointwise(const LaunchReduce &L);
+
+// Kinetic energy of 1-D instances: kin[inst] = sum_k k^2 |u^_k|^2 / (2 mu N)
+// (times the cell size on the host).
+struct LaunchKin1D {
+    const Item1D *items;
+    int n_items;
+    int P;
+    const int *perm;
+    const InstDev *insts;
+    const void *psi;
+    int c64;
+    double *kin;  // [n_inst]
+    hipStream_t stream;
+};
+hipError_t launch_kinetic_1d(const LaunchKin1D &L);
+
+}  // namespace hfgpe

@@ -1,0 +1,78 @@
+// layout.hpp -- device-side data layout shared by the host runtime and the
+// kernels: per-instance descriptors, per-stage coefficient records and work
+// items.  All floating-point fields are FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace hfgpe {
+
+constexpr int kMaxStages = 16;
+
+struct SinMod {
+    double v0, amp, freq, phase;  // v(t) = v0 (1 + amp sin(freq t + phase))
+};
+
+struct VFac {
+    double c0, c2, c4, gs, k, phi;  // (c0 + c2 x^2 + c4 x^4) exp(-x^2/gs) cos(k x + phi)
+};
+
+// One instance as the kernels see it.
+struct InstDev {
+    int64_t offset;  // first complex element in the packed buffer
+    int ndim;
+    int n[3];
+    int logn[3];
+    int pad_;
+    double lo[3];
+    double dx[3];
+    double kscale[3];  // 2 pi / L_j
+    double mu;
+    double eps;
+    SinMod om[3];
+    SinMod sig;
+    VFac vf[3];
+};
+
+// The pointwise x-space phase applied after stage i of a step:
+//   u <- exp(-i (sum_j chi_j x_j^2/2 + w eps V_I(x) + s |u|^2)) u
+// (chi merges the closing chirp f_i with the next opening chirp e_{i+1};
+// w = dt * b (merged B weight); s = w * sigma(tau)), and the kinetic
+// coefficient g_j of the stage's drift.  64 bytes.
+struct Rec {
+    double g[3];
+    double chi[3];
+    double w;
+    double s;
+};
+
+// Composition in device-friendly form (Eq. prod-gen; b has m+1 weights;
+// cum[i] = a_0 + ... + a_{i-1}, the stage-start offsets within a step).
+struct SchemeDev {
+    int m;
+    int rule;
+    int ndim;
+    int pad_;
+    double a[kMaxStages];
+    double b[kMaxStages + 1];
+    double cum[kMaxStages + 1];
+};
+
+// A group of `count` same-size 1-D instances processed by one workgroup.
+struct Item1D {
+    int first;  // index into the plan's instance permutation
+    int count;
+    int logn;
+    int pad_;
+};
+
+__host__ __device__ inline double vfactor(const VFac &v, double x)
+{
+    double x2 = x * x;
+    double poly = v.c0 + x2 * (v.c2 + x2 * v.c4);
+    double gauss = (v.gs > 0.0) ? exp(-x2 / v.gs) : 1.0;
+    return poly * gauss * cos(v.k * x + v.phi);
+}
+
+}  // namespace hfgpe

@@ -1,0 +1,150 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared
+symbol, its host-only pieces (scheme tables, closed-form stage coefficients,
+argument validation) agree with the oracle and the header.  No GPU compute."""
+import ctypes
+import math
+import os
+import re
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1007_3470_amd as pkg
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hfgpe.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hfgpe_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.load()
+    names = declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(pkg.SYMBOLS)
+
+
+def test_version_and_status_strings():
+    lib = pkg.load()
+    ma, mi = ctypes.c_int(), ctypes.c_int()
+    assert lib.hfgpe_version(ctypes.byref(ma), ctypes.byref(mi)) == 0
+    assert (ma.value, mi.value) == (0, 1)
+    for code in range(-8, 1):
+        assert lib.hfgpe_status_string(code).decode() != "unknown status"
+    assert lib.hfgpe_status_string(-99).decode() == "unknown status"
+
+
+@pytest.mark.parametrize("name", ["leapfrog", "lie", "srkn6_4", "ni4_82", "ni5_84"])
+def test_scheme_presets_match_oracle_tables(name):
+    a, b = pkg.scheme_preset(name)
+    oa, ob = oracle.scheme_coefficients(name)
+    assert np.array_equal(a, oa) and np.array_equal(b, ob)
+
+
+def test_unknown_scheme_rejected():
+    with pytest.raises(pkg.HfgpeError) as e:
+        pkg.scheme_preset("nope")
+    assert e.value.code == -1
+
+
+RULES = ["exact_const", "cf4", "magnus6"]
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("scheme", ["leapfrog", "ni5_84", "srkn6_4", "ni4_82"])
+@pytest.mark.parametrize("dt", [1e-3, 0.05, -0.02])
+def test_closed_forms_match_oracle_matrix_route(rule, scheme, dt):
+    rng = np.random.default_rng(abs(hash((rule, scheme, dt))) % 2 ** 32)
+    for _ in range(5):
+        mu = float(rng.uniform(0.5, 2.0))
+        amp = 0.0 if rule == "exact_const" else float(rng.uniform(0, 0.5))
+        om = (float(rng.uniform(0.5, 2.0)), amp, float(rng.uniform(0.5, 3)), float(rng.uniform(0, 6)))
+        inst = W.Instance(2, (8, 8, 1), (-1, -1, 0), (1, 1, 1), mu=mu,
+                          omega=(om, (1.3, 0.0, 0.0, 0.0), W.CONST_OMEGA))
+        tn = float(rng.uniform(0, 10))
+        lib_c = pkg.stage_coeffs_params(inst, scheme, rule, dt, tn)
+        orc_c = oracle.stage_coeffs(inst, scheme, rule, dt, tn)
+        assert np.allclose(lib_c, orc_c, rtol=1e-12, atol=0), np.abs(lib_c / orc_c - 1).max()
+
+
+def _create(instances, scheme="leapfrog", rule="cf4", dtype=1, dt=1e-3, m=None, a=None, b=None):
+    lib = pkg.load()
+    if a is None:
+        a, b = pkg.scheme_preset(scheme)
+    ca, cb = (ctypes.c_double * len(a))(*a), (ctypes.c_double * len(b))(*b)
+    sch = pkg.Scheme(len(a) if m is None else m, ca, cb, pkg.HO_RULES[rule])
+    n = len(instances)
+    g = (pkg.Grid * max(1, n))(*[pkg.make_grid(i) for i in instances])
+    p = (pkg.Params * max(1, n))(*[pkg.make_params(i) for i in instances])
+    h = ctypes.c_void_p()
+    rc = lib.hfgpe_plan_create(ctypes.byref(h), n, g, p, ctypes.byref(sch), dtype, dt, None, None)
+    if rc == 0:
+        lib.hfgpe_plan_destroy(h)
+    return rc
+
+
+def _gpu_or_nodevice(rc):
+    # valid arguments: OK on a gfx950 box, NO_DEVICE without one
+    return rc in (0, -8)
+
+
+def test_plan_validation_codes():
+    base = W.gpe_1d(n=64, nsteps=0).instances[0]
+    assert _gpu_or_nodevice(_create([base]))
+    assert _create([replace(base, n=(48, 1, 1))]) == -2              # not a power of two
+    assert _create([replace(base, n=(8192, 1, 1))]) == -2            # beyond the 1-D limit
+    assert _create([replace(base, n=(64, 2, 1))]) == -2              # unused axis not 1
+    assert _create([replace(base, mu=0.0)]) == -1
+    assert _create([replace(base, hi=(-20.0, 1.0, 1.0))]) == -1      # empty box
+    assert _create([base], dt=0.0) == -1
+    assert _create([base], dt=float("nan")) == -1
+    assert _create([base], dtype=7) == -1
+    assert _create([base], m=0) == -1
+    assert _create([base], a=[0.0], b=[0.5, 0.5]) == -1              # zero stage
+    assert _create([base], rule="exact_const") == -1                 # omega varies in time
+    assert _create([base], dt=3.0) == -3                             # beyond the first zero of g
+    neg = replace(base, omega=((-1.0, 0.0, 0.0, 0.0),) + base.omega[1:])
+    assert _create([neg]) == -4
+    assert _create([replace(base, omega=((1.0, 1.2, 1.0, 0.0),) + base.omega[1:])]) == -4
+    two = [base, replace(base, ndim=2, n=(64, 64, 1))]
+    assert _create(two) == -1                                        # mixed dimensions
+
+
+def test_exact_rule_singularity_bound():
+    c1 = W.coherent_1d().instances[0]
+    assert _gpu_or_nodevice(_create([c1], rule="exact_const", dt=3.1))
+    assert _create([c1], rule="exact_const", dt=3.2) == -3
+    assert _gpu_or_nodevice(_create([c1], rule="exact_const", dt=-3.1))
+
+
+def test_empty_plan_is_valid_without_device():
+    lib = pkg.load()
+    a, b = pkg.scheme_preset("leapfrog")
+    ca, cb = (ctypes.c_double * 1)(*a), (ctypes.c_double * 2)(*b)
+    sch = pkg.Scheme(1, ca, cb, 1)
+    h = ctypes.c_void_p()
+    assert lib.hfgpe_plan_create(ctypes.byref(h), 0, None, None, ctypes.byref(sch), 0, 1e-3,
+                                 None, None) == 0
+    off = (ctypes.c_int64 * 1)()
+    assert lib.hfgpe_instance_offsets(h, off) == 0 and off[0] == 0
+    assert lib.hfgpe_evolve(h, None, 0.0, 10) == 0
+    assert lib.hfgpe_norm(h, None, None) == 0
+    assert lib.hfgpe_plan_destroy(h) == 0
+    assert lib.hfgpe_plan_destroy(None) == 0
+
+
+def test_null_arguments_rejected():
+    lib = pkg.load()
+    assert lib.hfgpe_plan_create(None, 0, None, None, None, 0, 1e-3, None, None) == -1
+    assert lib.hfgpe_evolve(None, None, 0.0, 1) == -1
+    assert lib.hfgpe_norm(None, None, None) == -1
+    assert lib.hfgpe_instance_offsets(None, None) == -1
+    assert lib.hfgpe_stage_coeffs(None, 0, 0.0, None) == -1

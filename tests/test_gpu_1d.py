@@ -1,0 +1,221 @@
+"""GPU parity of the 1-D resident HIP path against the CPU oracle.
+
+Every test calls the library through the C ABI (Python binding) on cuda:0 and
+compares element by element with the oracle on the same seeded inputs.
+Tolerances: relative L2 1e-11 for the FP64 (c128) path, 5e-5 for c64."""
+import math
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-11, "c64": 5e-5}
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1007_3470_amd as p
+    p.load()
+    return p
+
+
+def run_gpu(pkg, w, dtype, **kw):
+    import torch
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, **kw)
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, w.t0, w.nsteps)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    return plan, buf, plan.unpack(buf)
+
+
+def oracle_run(w, k, nsteps=None, t0=None):
+    return oracle.evolve(w.instances[k], w.psi0[k], w.scheme, w.ho_rule, w.dt,
+                         w.t0 if t0 is None else t0, w.nsteps if nsteps is None else nsteps)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# coherent state (linear, constant omega): oracle and closed form
+# ---------------------------------------------------------------------------
+def test_coherent_state_full_run(pkg):
+    w = W.coherent_1d()
+    _, buf, got = run_gpu(pkg, w, "c128")
+    ref = oracle_run(w, 0)
+    T = w.dt * w.nsteps
+    x = w.instances[0].axis(0)
+    ex = math.pi ** -0.25 * np.exp(-(x - math.cos(T)) ** 2 / 2) * np.exp(
+        1j * (-x * math.sin(T) + math.sin(2 * T) / 4 - T / 2))
+    e_orc, e_ex = W.rel_l2(got[0], ref), W.rel_l2(got[0], ex)
+    say("coherent: vs oracle %.3e, vs closed form %.3e" % (e_orc, e_ex))
+    assert e_orc < 1e-11 and e_ex < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# the 1-D GPE with time-dependent trap: full 10^4 steps, both precisions
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def gpe1d_ref():
+    w = W.gpe_1d()
+    return w, oracle_run(w, 0)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_gpe_1d_full_run(pkg, gpe1d_ref, dtype):
+    w, ref = gpe1d_ref
+    plan, buf, got = run_gpu(pkg, w, dtype)
+    err = W.rel_l2(got[0], ref)
+    nrm = plan.norm(buf)[0]
+    say("gpe_1d %s: rel_l2 %.3e norm-1 %.3e" % (dtype, err, nrm - 1))
+    assert err < TOL[dtype]
+    assert abs(nrm - oracle.norm(w.instances[0], ref)) < (1e-12 if dtype == "c128" else 1e-5)
+
+
+# ---------------------------------------------------------------------------
+# ragged batch: every supported size in one plan, incl. degenerate ones
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_ragged_batch_all_sizes(pkg, dtype):
+    sizes = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096)
+    w = W.batch_1d(n_inst=2 * len(sizes), sizes=sizes, nsteps=30, seed=3)
+    # make sure each size appears
+    insts = list(w.instances)
+    for k, n in enumerate(sizes):
+        inst = insts[k]
+        L = max(n, 64) / 64.0
+        insts[k] = replace(inst, n=(n, 1, 1), lo=(-L, 0.0, 0.0), hi=(L, 1.0, 1.0))
+    psis = []
+    for k, inst in enumerate(insts):
+        x = inst.axis(0)
+        psis.append(W._normalise(inst, np.exp(-(x - 0.1 * k / len(insts)) ** 2 / 2).astype(complex)))
+    w = replace(w, instances=insts, psi0=psis)
+    _, _, got = run_gpu(pkg, w, dtype)
+    for k, inst in enumerate(w.instances):
+        err = W.rel_l2(got[k], oracle_run(w, k))
+        say("ragged %s k=%d N=%d rel_l2 %.3e" % (dtype, k, inst.n[0], err))
+        assert err < TOL[dtype], (k, inst.n[0], err)
+
+
+# ---------------------------------------------------------------------------
+# every composition and harmonic-oscillator rule (FSAL merge vs unmerged)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme", ["leapfrog", "lie", "ni4_82", "ni5_84", "srkn6_4"])
+@pytest.mark.parametrize("rule", ["cf4", "magnus6"])
+def test_schemes_and_rules(pkg, scheme, rule):
+    w = W.batch_1d(n_inst=4, sizes=(128, 512), nsteps=25, seed=11, scheme=scheme, rule=rule)
+    _, _, got = run_gpu(pkg, w, "c128")
+    for k in range(len(w.instances)):
+        err = W.rel_l2(got[k], oracle_run(w, k))
+        say("scheme %s rule %s k=%d rel_l2 %.3e" % (scheme, rule, k, err))
+        assert err < 1e-11
+
+
+def test_exact_rule_general_mu(pkg):
+    w = W.coherent_1d(n=512, lo=-12.0, hi=12.0, x0=0.8, dt=0.05, nsteps=200, omega=1.3, mu=2.0)
+    _, _, got = run_gpu(pkg, w, "c128")
+    assert W.rel_l2(got[0], oracle_run(w, 0)) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# schedules: chunking, plain mode, single-instance vs batch (bitwise in FP64)
+# ---------------------------------------------------------------------------
+def test_schedules_agree_bitwise_fp64(pkg):
+    w = W.batch_1d(n_inst=24, sizes=(256, 512, 1024, 2048), nsteps=37, seed=21)
+    _, _, a = run_gpu(pkg, w, "c128")
+    _, _, b = run_gpu(pkg, w, "c128", steps_per_launch=5)
+    _, _, c = run_gpu(pkg, w, "c128", plain=True)
+    for k in range(len(w.instances)):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+    for k in (0, 7, 23):
+        _, _, alone = run_gpu(pkg, W.subset(w, [k]), "c128")
+        assert np.array_equal(alone[0], a[k]), k
+
+
+def test_evolve_split_equals_single_call(pkg):
+    import torch
+    w = W.batch_1d(n_inst=5, sizes=(256, 1024), nsteps=40, seed=8)
+    plan, buf, full = run_gpu(pkg, w, "c128")
+    buf2 = plan.pack(w.psi0)
+    plan.evolve(buf2, w.t0, 15)
+    plan.evolve(buf2, w.t0 + 15 * w.dt, 25)
+    torch.cuda.synchronize()
+    split = plan.unpack(buf2)
+    for k in range(5):
+        assert W.rel_l2(split[k], full[k]) < 1e-13
+
+
+def test_time_reversibility_gpu(pkg):
+    import torch
+    w = W.batch_1d(n_inst=3, sizes=(512,), nsteps=50, seed=9, scheme="ni5_84")
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", w.dt)
+    back = pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", -w.dt)
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, 0.2, 50)
+    back.evolve(buf, 0.2 + 50 * w.dt, 50)
+    torch.cuda.synchronize()
+    got = plan.unpack(buf)
+    for k in range(3):
+        assert W.rel_l2(got[k], w.psi0[k]) < 1e-12
+
+
+def test_zero_steps_and_empty(pkg):
+    import torch
+    w = W.batch_1d(n_inst=2, sizes=(64,), nsteps=0, seed=1)
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", w.dt)
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, 0.0, 0)
+    torch.cuda.synchronize()
+    got = plan.unpack(buf)
+    assert all(np.array_equal(got[k], w.psi0[k]) for k in range(2))
+    empty = pkg.Plan([], "leapfrog", "cf4", "c64", 1e-3)
+    empty.evolve(torch.zeros(1, dtype=torch.complex64, device="cuda"), 0.0, 5)
+    assert empty.norm(torch.zeros(1, dtype=torch.complex64, device="cuda")).size == 0
+
+
+# ---------------------------------------------------------------------------
+# observables
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_norm_and_energy_match_oracle(pkg, dtype):
+    w = W.batch_1d(n_inst=12, sizes=(64, 256, 1024, 2048, 4096), nsteps=20, seed=4)
+    plan, buf, got = run_gpu(pkg, w, dtype)
+    nrm = plan.norm(buf)
+    en = plan.energy(buf, w.t0 + w.nsteps * w.dt)
+    tol = 1e-12 if dtype == "c128" else 1e-6
+    for k, inst in enumerate(w.instances):
+        # compare on the GPU's own (rounded) state so only the reductions differ
+        assert abs(nrm[k] - oracle.norm(inst, got[k])) < tol * max(1.0, abs(nrm[k]))
+        ref = oracle.energy(inst, got[k], w.t0 + w.nsteps * w.dt)
+        assert np.allclose(en[k], ref, rtol=1e-12, atol=1e-12), (k, en[k], ref)
+
+
+# ---------------------------------------------------------------------------
+# the batched workload at full size (4096 instances, 5000 steps), sampled
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_batch_1d_full_size_sampled(pkg, dtype):
+    w = W.batch_1d()
+    plan, buf, got = run_gpu(pkg, w, dtype)
+    # one sampled instance of each grid size
+    picks = {}
+    for k, inst in enumerate(w.instances):
+        picks.setdefault(inst.n[0], k)
+    for n, k in sorted(picks.items()):
+        err = W.rel_l2(got[k], oracle_run(w, k))
+        say("batch_1d full %s instance %d N=%d rel_l2 %.3e" % (dtype, k, n, err))
+        assert err < TOL[dtype]
+    nrm = plan.norm(buf)
+    n0 = np.array([oracle.norm(i, p) for i, p in zip(w.instances, w.psi0)])
+    drift = np.abs(nrm - n0).max()
+    say("batch_1d full %s max norm drift %.3e" % (dtype, drift))
+    assert drift < (1e-11 if dtype == "c128" else 1e-4)
