@@ -1,0 +1,208 @@
+"""Benchmark: batched 1-D Hermite-Fourier GPE time stepping on one MI355X.
+
+Workload: 4096 independent 1-D GPE instances, grid sizes drawn from
+{256, 512, 1024, 2048} on [-N/64, N/64) (dx = 1/32), omega(t) = w0 (1 + a sin(nu t)),
+sigma ~ U[-1, 50], eps V_I = 0.01 cos 3x, BAB leapfrog with the fourth-order
+commutator-free HO rule, dt = 1e-3; inputs seeded (workloads.batch_1d).
+
+One benchmark "step" advances every instance of the batch by one time step
+(one FFT pair per instance).  The headline value is the complex64-storage
+batched solver (state resident on chip for a chunk of steps, one launch per
+chunk) in grid-point-steps per second; the plain FP64 solver (complex128, one
+launch per step per grid size) and the complex128 batched solver are timed
+beside it, and the relative L2 error of every result is stated.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "grid-point-steps/s + %HBM peak, c64 batched vs FP64 plain, at stated L2 error"
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hf1d_batch1d.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1007_3470_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def flops_per_gp_step(n: int, m: int) -> float:
+    """Algorithmic flops of one grid point advanced one step: per stage the
+    radix-2 count of an FFT pair (2 x 5 log2 N per point), two complex phase
+    multiplies (12) and the phase arguments (x-phase 5, drift 2)."""
+    return m * (10.0 * np.log2(n) + 19.0)
+
+
+def timed_evolve(pkg, torch, w, dtype, K, warmup, **kw):
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, profile=True, **kw)
+    if warmup > 0:
+        scratch = plan.pack(w.psi0)
+        plan.evolve(scratch, 0.0, warmup)
+        torch.cuda.synchronize()
+        del scratch
+    plan.profile()  # reset counters
+    buf = plan.pack(w.psi0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    plan.evolve(buf, 0.0, K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    step_ms, coeff_ms, launches = plan.profile()
+    status = plan.device_status()
+    if status != 0:
+        raise RuntimeError("device status %d" % status)
+    return plan, buf, wall, gpu_ms, step_ms, coeff_ms, launches
+
+
+def load_traffic(src_hash):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != src_hash:
+        return None  # kernel changed since the counters were taken
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(w, K, per_size, gpu_out):
+    """The oracle on a bounded sample: the first `per_size` instances of each
+    grid size, advanced the same K steps; returns rate and parity."""
+    import oracle
+    import workloads as W
+    picks = {}
+    for k, inst in enumerate(w.instances):
+        lst = picks.setdefault(inst.n[0], [])
+        if len(lst) < per_size:
+            lst.append(k)
+    sample = sorted(k for lst in picks.values() for k in lst)
+    t0 = time.perf_counter()
+    refs = {k: oracle.evolve(w.instances[k], w.psi0[k], w.scheme, w.ho_rule, w.dt, 0.0, K)
+            for k in sample}
+    dt = time.perf_counter() - t0
+    pts = sum(w.instances[k].n[0] for k in sample)
+    errs = {name: max(W.rel_l2(out[k], refs[k]) for k in sample) for name, out in gpu_out.items()}
+    return {"value": pts * K / dt, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d instances (%d per grid size) x %d steps, single-threaded C oracle, "
+                      "%.1f s" % (len(sample), per_size, K, dt)}, errs
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-per-size", type=int, default=8,
+                    help="oracle sample: instances per grid size (0 disables)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(instances would be sharded across GPUs with no exchange); use --gpus 1",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_1007_3470_amd as pkg
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    pkg.load()
+    K, WU = args.steps, args.warmup
+    w = W.batch_1d(nsteps=K)
+    npts = w.points
+    m = len(pkg.scheme_preset(w.scheme)[0])
+    sizes = np.array([i.n[0] for i in w.instances])
+    flops_per_step = float(sum(n * flops_per_gp_step(n, m) for n in sizes))
+
+    # headline: complex64 storage, batched resident solver
+    plan64, buf64, wall64, ms64, kms64, cms64, nl64 = timed_evolve(pkg, torch, w, "c64", K, WU)
+    out64 = plan64.unpack(buf64)
+    # complex128 batched and the plain FP64 solver
+    plan128, buf128, wall128, ms128, kms128, cms128, nl128 = timed_evolve(pkg, torch, w, "c128", K, WU)
+    out128 = plan128.unpack(buf128)
+    plain = None
+    if not args.no_plain:
+        pl, bufp, wallp, msp, kmsp, cmsp, nlp = timed_evolve(pkg, torch, w, "c128", K,
+                                                             min(WU, 20), plain=True)
+        outp = pl.unpack(bufp)
+        plain = {"value": npts * K / wallp, "ms_per_step": wallp * 1e3 / K, "launches": nlp,
+                 "max_rel_l2_vs_c128_batched": max(W.rel_l2(a, b) for a, b in zip(outp, out128))}
+    errs64 = np.array([W.rel_l2(a, b) for a, b in zip(out64, out128)])
+
+    value = npts * K / wall64
+    # roofline of the dominant kernel: the resident step kernel, FP64 ALU bound
+    avg_launch_s = kms64 / 1e3 / max(1, nl64)
+    flops_per_launch = flops_per_step * K / max(1, nl64)
+    achieved = flops_per_launch / avg_launch_s / 1e12
+    traffic = load_traffic(kernel_source_hash())
+    roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+            "kernel": "hf1d_kernel<float2> (resident 1-D step)",
+            "avg_launch_ms": avg_launch_s * 1e3, "launches": nl64,
+            "flops_per_gp_step": "10 log2 N + 19 per stage"}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "grid-point-steps/s", "n_gpus": 1,
+        "steps": K, "warmup": WU, "ms_per_step": wall64 * 1e3 / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch_1d: 4096 x 1-D GPE, N in {256,512,1024,2048}, L=N/64, "
+                               "leapfrog + CF4, dt=1e-3, %d steps" % K,
+                   "instances": len(w.instances), "grid_points": npts, "storage": "c64",
+                   "arithmetic": "f64", "parallelism": "single GPU, batched resident kernel"},
+        # bytes a design with one HBM read + write of the state per stage would
+        # move at this rate (16 B per grid-point-step for c64), against 8 TB/s
+        "hbm_equivalent": {"GBs": 16.0 * m * value / 1e9,
+                           "frac_of_peak": 16.0 * m * value / 1e9 / HBM_PEAK_GBS},
+        "gpu_event_ms": {"c64": ms64, "c128": ms128},
+        "c128_batched": {"value": npts * K / wall128, "ms_per_step": wall128 * 1e3 / K},
+        "fp64_plain": plain,
+        "speedup_vs_fp64_plain": (value / plain["value"]) if plain else None,
+        "l2": {"c64_vs_c128_max": float(errs64.max()), "c64_vs_c128_median": float(np.median(errs64))},
+        "roofline": roof,
+        "wall_s": {"c64": wall64, "c128": wall128},
+    }
+    if args.copy_calibration:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = {"read": 512 << 20, "write": 512 << 20}
+    if args.cpu_per_size > 0:
+        cpu, errs = cpu_baseline(w, K, args.cpu_per_size, {"c64": out64, "c128": out128})
+        line["cpu_baseline"] = cpu
+        line["l2"]["c64_vs_oracle_sample_max"] = errs["c64"]
+        line["l2"]["c128_vs_oracle_sample_max"] = errs["c128"]
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

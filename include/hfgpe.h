@@ -117,6 +117,8 @@ typedef struct {
     int plain;             /* 1 = reference schedule: one launch per step per
                               grid-size group, no graphs */
     int use_graph;         /* 1 = replay chunks from a captured hipGraph */
+    int profile;           /* 1 = bracket every step-kernel launch with HIP
+                              events on the plan's stream (hfgpe_profile) */
 } hfgpe_options;
 
 typedef struct hfgpe_plan hfgpe_plan;
@@ -181,6 +183,11 @@ int hfgpe_scheme_preset(const char *name, int *m, double *a, double *b);
 /* Device-side error word raised by the coefficient kernel since the last
  * call (0 or a status code); synchronises and clears it. */
 int hfgpe_device_status(hfgpe_plan *plan);
+
+/* With opts.profile set: total milliseconds spent in the step kernels and
+ * in the coefficient kernel, and the number of step-kernel launches, since
+ * the last call (synchronises the stream; resets the counters). */
+int hfgpe_profile(hfgpe_plan *plan, double *step_ms, double *coeff_ms, int64_t *step_launches);
 
 const char *hfgpe_status_string(int status);
 int hfgpe_version(int *major, int *minor);

@@ -28,7 +28,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "si
 SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", "hfgpe_evolve",
            "hfgpe_norm", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
            "hfgpe_scheme_preset",
-           "hfgpe_device_status", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
+           "hfgpe_device_status", "hfgpe_profile", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
 
 
 class HfgpeError(RuntimeError):
@@ -63,7 +63,7 @@ class Scheme(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("steps_per_launch", ctypes.c_int), ("plain", ctypes.c_int),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("profile", ctypes.c_int)]
 
 
 _lib = None
@@ -92,6 +92,7 @@ def load() -> ctypes.CDLL:
                                               ctypes.c_double, dp]
     lib.hfgpe_scheme_preset.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), dp, dp]
     lib.hfgpe_device_status.argtypes = [vp]
+    lib.hfgpe_profile.argtypes = [vp, dp, dp, i64p]
     lib.hfgpe_status_string.argtypes = [ctypes.c_int]
     lib.hfgpe_status_string.restype = ctypes.c_char_p
     lib.hfgpe_version.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -153,7 +154,8 @@ class Plan:
 
     def __init__(self, instances: Sequence, scheme: str = "leapfrog", ho_rule: str = "cf4",
                  dtype: str = "c128", dt: float = 1e-3, steps_per_launch: int = 0,
-                 plain: bool = False, use_graph: bool = False, stream=None,
+                 plain: bool = False, use_graph: bool = False, profile: bool = False,
+                 stream=None,
                  a: Optional[Sequence[float]] = None, b: Optional[Sequence[float]] = None):
         import torch
         self.lib = load()
@@ -167,7 +169,8 @@ class Plan:
         sch = Scheme(len(a), self._a, self._b, HO_RULES[ho_rule])
         grids = (Grid * max(1, self.n_inst))(*[make_grid(i) for i in instances])
         params = (Params * max(1, self.n_inst))(*[make_params(i) for i in instances])
-        opts = Options(int(steps_per_launch), int(bool(plain)), int(bool(use_graph)))
+        opts = Options(int(steps_per_launch), int(bool(plain)), int(bool(use_graph)),
+                       int(bool(profile)))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -227,6 +230,14 @@ class Plan:
         _check(self.lib.hfgpe_stage_coeffs(self.handle, int(inst), float(tn), out),
                "hfgpe_stage_coeffs")
         return np.array(out[:]).reshape(m, ndim, 3)
+
+    def profile(self):
+        """(step-kernel ms, coefficient-kernel ms, step-kernel launches) since
+        the last call, from HIP events on the plan's stream."""
+        sm, cm, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(self.lib.hfgpe_profile(self.handle, ctypes.byref(sm), ctypes.byref(cm),
+                                      ctypes.byref(n)), "hfgpe_profile")
+        return sm.value, cm.value, n.value
 
     def device_status(self) -> int:
         return int(self.lib.hfgpe_device_status(self.handle))

@@ -75,6 +75,8 @@ struct hfgpe_plan {
     double *d_part = nullptr;
     double *d_kin = nullptr;
     int nblk = 1;
+    // profiling: (start, stop) event pairs recorded on the plan's stream
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_coeff, ev_pool;
 
     ~hfgpe_plan()
     {
@@ -88,6 +90,11 @@ struct hfgpe_plan {
         if (d_rec_open) (void)hipFree(d_rec_open);
         if (d_part) (void)hipFree(d_part);
         if (d_kin) (void)hipFree(d_kin);
+        for (auto *v : {&ev_step, &ev_coeff, &ev_pool})
+            for (auto &e : *v) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
     }
 };
 
@@ -221,6 +228,18 @@ void build_groups_1d(hfgpe_plan &P, bool plain)
 }
 
 }  // namespace
+
+static int take_events(hfgpe_plan *P, std::pair<hipEvent_t, hipEvent_t> &out)
+{
+    if (!P->ev_pool.empty()) {
+        out = P->ev_pool.back();
+        P->ev_pool.pop_back();
+        return HFGPE_OK;
+    }
+    HIP_TRY(hipEventCreate(&out.first));
+    HIP_TRY(hipEventCreate(&out.second));
+    return HFGPE_OK;
+}
 
 extern "C" {
 
@@ -452,7 +471,17 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
         C.nsteps_total = nsteps;
         C.err = P->d_err;
         C.stream = P->stream;
+        std::pair<hipEvent_t, hipEvent_t> ec{};
+        if (P->opts.profile) {
+            int rc = take_events(P, ec);
+            if (rc) return rc;
+            HIP_TRY(hipEventRecord(ec.first, P->stream));
+        }
         HIP_TRY(launch_coeff(C));
+        if (P->opts.profile) {
+            HIP_TRY(hipEventRecord(ec.second, P->stream));
+            P->ev_coeff.push_back(ec);
+        }
         for (int sb = 0; sb < k; sb += per_launch) {
             int kk = std::min(per_launch, k - sb);
             for (auto &g : P->groups) {
@@ -472,7 +501,17 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
                 L.apply_opening = (s0 == 0 && sb == 0) ? 1 : 0;
                 L.c64 = P->dtype == HFGPE_C64;
                 L.stream = P->stream;
+                std::pair<hipEvent_t, hipEvent_t> es{};
+                if (P->opts.profile) {
+                    int rc = take_events(P, es);
+                    if (rc) return rc;
+                    HIP_TRY(hipEventRecord(es.first, P->stream));
+                }
                 HIP_TRY(launch_hf1d(L));
+                if (P->opts.profile) {
+                    HIP_TRY(hipEventRecord(es.second, P->stream));
+                    P->ev_step.push_back(es);
+                }
             }
         }
     }
@@ -597,6 +636,31 @@ int hfgpe_stage_coeffs_params(const hfgpe_params *params, int ndim, const hfgpe_
             out[(i * ndim + j) * 3 + 1] = q.g;
             out[(i * ndim + j) * 3 + 2] = q.e;
         }
+    }
+    return HFGPE_OK;
+}
+
+int hfgpe_profile(hfgpe_plan *P, double *step_ms, double *coeff_ms, int64_t *step_launches)
+{
+    if (!P) return HFGPE_E_INVALID_ARG;
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    double ts = 0.0, tc = 0.0;
+    for (auto &e : P->ev_step) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+        ts += ms;
+    }
+    for (auto &e : P->ev_coeff) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.first, e.second));
+        tc += ms;
+    }
+    if (step_ms) *step_ms = ts;
+    if (coeff_ms) *coeff_ms = tc;
+    if (step_launches) *step_launches = (int64_t)P->ev_step.size();
+    for (auto *v : {&P->ev_step, &P->ev_coeff}) {
+        P->ev_pool.insert(P->ev_pool.end(), v->begin(), v->end());
+        v->clear();
     }
     return HFGPE_OK;
 }

@@ -14,7 +14,7 @@
 // movement.  Twiddles of passes 1.. are computed once per launch (sincospi of
 // exact dyadic angles) and stay in registers; phases use the FP64 cis_neg.
 // Storage: Store = float2 (c64) or double2 (c128) in HBM; Xch = the LDS
-// exchange type.  Arithmetic is FP64 throughout.
+// exchange type (FP64 for both).  Arithmetic is FP64 throughout.
 #include <hip/hip_runtime.h>
 
 #include "coeff.hpp"
@@ -336,7 +336,10 @@ static hipError_t launch_store(const Launch1D &L)
 hipError_t launch_hf1d(const Launch1D &L)
 {
     if (L.n_items <= 0) return hipSuccess;
-    if (L.c64) return launch_store<float2, float2>(L);
+    // The LDS exchange is FP64 for both storage types: rounding the exchanged
+    // values to FP32 costs conversions on every pass and, over thousands of
+    // steps of a strongly nonlinear instance, pushes the c64 error past 5e-5.
+    if (L.c64) return launch_store<float2, double2>(L);
     return launch_store<double2, double2>(L);
 }
 
