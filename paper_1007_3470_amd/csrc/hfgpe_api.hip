@@ -75,6 +75,11 @@ struct hfgpe_plan {
     double *d_part = nullptr;
     double *d_kin = nullptr;
     int nblk = 1;
+    double *d_vtab = nullptr;  // d-D: V_I factor per axis on its grid
+    int vtab_stride = 0;
+    double *d_kpart = nullptr;  // d-D kinetic-energy partials
+    int kin_nblk = 1;
+    int nd_grid = 1;
     // profiling: (start, stop) event pairs recorded on the plan's stream
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_coeff, ev_pool;
 
@@ -90,6 +95,8 @@ struct hfgpe_plan {
         if (d_rec_open) (void)hipFree(d_rec_open);
         if (d_part) (void)hipFree(d_part);
         if (d_kin) (void)hipFree(d_kin);
+        if (d_vtab) (void)hipFree(d_vtab);
+        if (d_kpart) (void)hipFree(d_kpart);
         for (auto *v : {&ev_step, &ev_coeff, &ev_pool})
             for (auto &e : *v) {
                 (void)hipEventDestroy(e.first);
@@ -334,7 +341,10 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         rc = validate_instance(params[k], nd, S, dt);
         if (rc) return rc;
     }
-    if (nd != 1 && n_inst > 0) return HFGPE_E_UNSUPPORTED_SHAPE;  // d-D kernels: see kern_nd
+    // d-D plans: every instance shares the grid shape (the boxes may differ)
+    for (int k = 1; k < n_inst && nd > 1; ++k)
+        for (int j = 0; j < 3; ++j)
+            if (grids[k].n[j] != grids[0].n[j]) return HFGPE_E_UNSUPPORTED_SHAPE;
     if (n_inst > 0) {
         rc = check_device();
         if (rc) return rc;
@@ -383,7 +393,9 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         return HFGPE_OK;
     }
 
-    build_groups_1d(*P, P->opts.plain != 0);
+    P->perm.resize(n_inst);
+    for (int k = 0; k < n_inst; ++k) P->perm[k] = k;
+    if (nd == 1) build_groups_1d(*P, P->opts.plain != 0);
     int64_t maxpts = 0;
     for (auto &I : P->insts) maxpts = std::max<int64_t>(maxpts, (int64_t)I.n[0] * I.n[1] * I.n[2]);
     P->nblk = (int)std::min<int64_t>(kReduceBlocksMax, std::max<int64_t>(1, (maxpts + 4095) / 4096));
@@ -427,6 +439,29 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
     for (auto &g : P->groups) {
         ALLOC_TRY(g.d_items, sizeof(Item1D) * g.items.size());
         COPY_TRY(g.d_items, g.items.data(), sizeof(Item1D) * g.items.size());
+    }
+    if (nd > 1) {
+        int ns = 1;
+        for (int j = 0; j < nd; ++j) ns = std::max(ns, P->insts[0].n[j]);
+        P->vtab_stride = ns;
+        std::vector<double> vt((size_t)n_inst * 3 * ns, 1.0);
+        for (int k = 0; k < n_inst; ++k)
+            for (int j = 0; j < nd; ++j)
+                for (int i = 0; i < P->insts[k].n[j]; ++i)
+                    vt[((size_t)k * 3 + j) * ns + i] =
+                        vfactor(P->insts[k].vf[j], P->insts[k].lo[j] + (double)i * P->insts[k].dx[j]);
+        ALLOC_TRY(P->d_vtab, sizeof(double) * vt.size());
+        COPY_TRY(P->d_vtab, vt.data(), sizeof(double) * vt.size());
+        int64_t pts = P->offsets[1];
+        P->kin_nblk = (int)std::min<int64_t>(64, std::max<int64_t>(1, pts / 65536));
+        ALLOC_TRY(P->d_kpart, sizeof(double) * (size_t)n_inst * P->kin_nblk);
+        // persistent workgroups for the axis passes: enough to fill the chip
+        int64_t groups = 0;
+        for (int j = 0; j < nd; ++j) {
+            int lG = nd_group_log(P->insts[0].n, j);
+            groups = std::max<int64_t>(groups, (int64_t)n_inst * ((pts / P->insts[0].n[j]) >> lG));
+        }
+        P->nd_grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, 2048));
     }
 #undef ALLOC_TRY
 #undef COPY_TRY
@@ -481,6 +516,44 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
         if (P->opts.profile) {
             HIP_TRY(hipEventRecord(ec.second, P->stream));
             P->ev_coeff.push_back(ec);
+        }
+        if (P->ndim > 1) {
+            for (int st = 0; st < k; ++st)
+                for (int i = 0; i < m; ++i)
+                    for (int j = 0; j < P->ndim; ++j) {
+                        LaunchND L;
+                        L.insts = P->d_insts;
+                        L.n_inst = P->n_inst;
+                        L.rec = P->d_rec;
+                        L.rec_open = P->d_rec_open;
+                        L.vtab = P->d_vtab;
+                        L.vtab_stride = P->vtab_stride;
+                        L.psi = d_psi;
+                        L.c64 = P->dtype == HFGPE_C64;
+                        L.ndim = P->ndim;
+                        for (int a = 0; a < 3; ++a) L.n[a] = P->insts[0].n[a];
+                        L.axis = j;
+                        L.stage = i;
+                        L.m = m;
+                        L.rec_steps = k;
+                        L.step = st;
+                        L.apply_open = (s0 == 0 && st == 0 && i == 0 && j == 0) ? 1 : 0;
+                        L.apply_close = (j == P->ndim - 1) ? 1 : 0;
+                        L.grid = P->nd_grid;
+                        L.stream = P->stream;
+                        std::pair<hipEvent_t, hipEvent_t> es{};
+                        if (P->opts.profile) {
+                            int rc = take_events(P, es);
+                            if (rc) return rc;
+                            HIP_TRY(hipEventRecord(es.first, P->stream));
+                        }
+                        HIP_TRY(launch_nd_pass(L));
+                        if (P->opts.profile) {
+                            HIP_TRY(hipEventRecord(es.second, P->stream));
+                            P->ev_step.push_back(es);
+                        }
+                    }
+            continue;
         }
         for (int sb = 0; sb < k; sb += per_launch) {
             int kk = std::min(per_launch, k - sb);
@@ -570,6 +643,28 @@ int hfgpe_energy(hfgpe_plan *P, const void *d_psi, double t, double *h_out)
     if (!P || (!h_out && P->n_inst > 0) || !std::isfinite(t)) return HFGPE_E_INVALID_ARG;
     if (P->n_inst == 0) return HFGPE_OK;
     if (!d_psi) return HFGPE_E_INVALID_ARG;
+    std::vector<double> kin(P->n_inst, 0.0);
+    if (P->ndim > 1) {
+        std::vector<double> kp((size_t)P->n_inst * P->kin_nblk);
+        for (int j = 0; j < P->ndim; ++j) {
+            LaunchND L;
+            std::memset(&L, 0, sizeof(L));
+            L.insts = P->d_insts;
+            L.n_inst = P->n_inst;
+            L.psi = const_cast<void *>(d_psi);
+            L.c64 = P->dtype == HFGPE_C64;
+            L.ndim = P->ndim;
+            for (int a = 0; a < 3; ++a) L.n[a] = P->insts[0].n[a];
+            L.axis = j;
+            L.stream = P->stream;
+            HIP_TRY(launch_kinetic_nd(L, P->kin_nblk, P->d_kpart));
+            HIP_TRY(hipMemcpyAsync(kp.data(), P->d_kpart, sizeof(double) * kp.size(), hipMemcpyDeviceToHost,
+                                   P->stream));
+            HIP_TRY(hipStreamSynchronize(P->stream));
+            for (int k = 0; k < P->n_inst; ++k)
+                kin[k] += ksum(&kp[(size_t)k * P->kin_nblk], P->kin_nblk, 1) / (2.0 * P->insts[k].mu);
+        }
+    }
     for (auto &g : P->groups) {
         LaunchKin1D K;
         K.items = g.d_items;
@@ -583,8 +678,8 @@ int hfgpe_energy(hfgpe_plan *P, const void *d_psi, double t, double *h_out)
         K.stream = P->stream;
         HIP_TRY(launch_kinetic_1d(K));
     }
-    std::vector<double> kin(P->n_inst);
-    HIP_TRY(hipMemcpyAsync(kin.data(), P->d_kin, sizeof(double) * P->n_inst, hipMemcpyDeviceToHost, P->stream));
+    if (P->ndim == 1)
+        HIP_TRY(hipMemcpyAsync(kin.data(), P->d_kin, sizeof(double) * P->n_inst, hipMemcpyDeviceToHost, P->stream));
     std::vector<double> part;
     int rc = run_reduce(P, d_psi, 1, t, part);
     if (rc) return rc;

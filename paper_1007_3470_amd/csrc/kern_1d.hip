@@ -19,129 +19,11 @@
 
 #include "coeff.hpp"
 #include "devmath.hpp"
+#include "fft_lds.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 
 namespace hfgpe {
-
-constexpr int kThreads1D = 256;
-constexpr int kPadShift = 4;  // one padding element every 16 in LDS
-
-__device__ __forceinline__ int lds_pad(int idx) { return idx + (idx >> kPadShift); }
-
-__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
-__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
-template <typename T>
-__device__ __forceinline__ T from_d2(double2 v);
-template <>
-__device__ __forceinline__ float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
-template <>
-__device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
-
-template <int P>
-struct Log2 {
-    static constexpr int value = (P <= 1) ? 0 : 1 + Log2<P / 2>::value;
-};
-template <>
-struct Log2<1> {
-    static constexpr int value = 0;
-};
-
-template <typename Xch, int P, int MAXS>
-struct Fft1D {
-    static constexpr int LOGP = Log2<P>::value;
-    static constexpr int NTW = (MAXS > 1) ? MAXS - 1 : 1;
-    static constexpr int PW = (P > 1) ? P - 1 : 1;
-
-    int logn, logT, S, r0log, tl;
-    Xch *buf;
-    double2 tw[NTW][PW];
-
-    __device__ void init(int logn_, int tl_, Xch *buf_)
-    {
-        logn = logn_;
-        tl = tl_;
-        buf = buf_;
-        logT = logn - LOGP;
-        S = (logn == 0 || LOGP == 0) ? 0 : (logn + LOGP - 1) / (LOGP > 0 ? LOGP : 1);
-        r0log = (S == 0) ? 0 : logn - LOGP * (S - 1);
-        const double invN = 1.0 / (double)(1 << logn);
-#pragma unroll
-        for (int s = 1; s < MAXS; ++s) {
-            if (s < S) {
-                int logL = r0log + LOGP * (s - 1);
-                int k = tl & ((1 << logL) - 1);
-                int slog = logn - logL - LOGP;
-#pragma unroll
-                for (int r = 1; r < P; ++r) {
-                    int e = (r * k) << slog;
-                    double sn, cs;
-                    sincospi(-2.0 * (double)e * invN, &sn, &cs);
-                    tw[s - 1][r - 1] = make_double2(cs, sn);
-                }
-            }
-        }
-    }
-
-    template <int R, int SGN>
-    __device__ __forceinline__ void pass0(double2 *u)
-    {
-        constexpr int NB = P / R;
-        const int T = 1 << logT;
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            double2 v[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = u[b + r * NB];
-            Dft<R, SGN>::run(v);
-            int j = tl + b * T;
-#pragma unroll
-            for (int rp = 0; rp < R; ++rp) buf[lds_pad(j * R + rp)] = from_d2<Xch>(v[rp]);
-        }
-    }
-
-    template <int SGN>
-    __device__ __forceinline__ void run(double2 *u)
-    {
-        if constexpr (P == 1) {
-            return;
-        } else {
-            if (S == 1) {  // N == P: one thread holds the whole instance
-                Dft<P, SGN>::run(u);
-                return;
-            }
-            switch (r0log) {
-            case 1: pass0<2, SGN>(u); break;
-            case 2: pass0<4, SGN>(u); break;
-            case 3: if constexpr (P >= 8) pass0<8, SGN>(u); break;
-            case 4: if constexpr (P >= 16) pass0<16, SGN>(u); break;
-            default: break;
-            }
-            const int T = 1 << logT;
-#pragma unroll
-            for (int s = 1; s < MAXS; ++s) {
-                if (s < S) {
-                    __syncthreads();
-#pragma unroll
-                    for (int c = 0; c < P; ++c) u[c] = to_d2(buf[lds_pad(tl + c * T)]);
-                    __syncthreads();
-#pragma unroll
-                    for (int r = 1; r < P; ++r)
-                        u[r] = (SGN < 0) ? cmul(u[r], tw[s - 1][r - 1]) : cmulc(u[r], tw[s - 1][r - 1]);
-                    Dft<P, SGN>::run(u);
-                    if (s < S - 1) {
-                        int logL = r0log + LOGP * (s - 1);
-                        int L = 1 << logL;
-                        int k = tl & (L - 1);
-                        int base = (tl - k) * P + k;
-#pragma unroll
-                        for (int rp = 0; rp < P; ++rp) buf[lds_pad(base + rp * L)] = from_d2<Xch>(u[rp]);
-                    }
-                }
-            }
-        }
-    }
-};
 
 template <typename Store, typename Xch, int P, int MAXS>
 __global__ __launch_bounds__(kThreads1D) void hf1d_kernel(const Item1D *__restrict__ items,

@@ -1,0 +1,305 @@
+// kern_nd.hip -- 2-D / 3-D Hermite-Fourier axis passes for gfx950.
+//
+// The d-D drift D(g) = F^-1 exp(-i sum_j g_j k_j^2/2) F factors into one 1-D
+// drift per axis (the kinetic phase is separable and the per-axis transforms
+// commute), so a stage is d axis passes, each one HBM read and one HBM write
+// of the state:
+//   pass j: load pencils along axis j  [opening x-phase on the first pass of
+//           an evolve call]  ->  FFT_j  ->  exp(-i g_j k_j^2/2)/N_j  ->
+//           FFT_j^-1  [merged closing x-phase on the last axis]  ->  store.
+// Workgroups are persistent over groups of G pencils.  Along x the G pencils
+// are consecutive rows and a pencil's points are consecutive lanes; along a
+// strided axis the G pencils are G consecutive x positions, lanes run over
+// the pencils first (coalesced rows of G elements) and LDS is interleaved by
+// pencil.  The drift factors of a thread's P wavenumbers are computed once per
+// (workgroup, instance) and reused for every pencil it processes.
+#include <hip/hip_runtime.h>
+
+#include "coeff.hpp"
+#include "devmath.hpp"
+#include "fft_lds.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace hfgpe {
+
+constexpr int kThreadsND = 256;
+
+struct NdShape {
+    int ndim;
+    int n[3];
+    int logn[3];
+};
+
+template <typename Store, int P, int MAXS>
+__global__ __launch_bounds__(kThreadsND) void hfnd_pass_kernel(
+    const InstDev *__restrict__ insts, int n_inst, const Rec *__restrict__ rec,
+    const Rec *__restrict__ rec_open, const double *__restrict__ vtab, int vtab_stride,
+    Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step,
+    int apply_open, int apply_close)
+{
+    constexpr int LOGP = Log2<P>::value;
+    constexpr int LDS_ELEMS = kThreadsND * P + ((kThreadsND * P) >> kPadShift);
+    __shared__ double2 lds[LDS_ELEMS];
+
+    const int lnj = sh.logn[axis];
+    const int nj = 1 << lnj;
+    const int logT = lnj - LOGP;
+    const int T = 1 << logT;
+    int lstride = 0;
+    for (int j = 0; j < axis; ++j) lstride += sh.logn[j];
+    const int ltot = sh.logn[0] + sh.logn[1] + sh.logn[2];
+    const int64_t npencil = (int64_t)1 << (ltot - lnj);
+    // G = 2^lG pencils per group; the block has exactly G * T threads
+    const int G = 1 << lG;
+    const int64_t gpi = npencil >> lG;  // groups per instance
+    const int tid = threadIdx.x;
+    int slot, tl;
+    Fft1D<double2, P, MAXS> fft;
+    if (axis == 0) {
+        slot = tid >> logT;
+        tl = tid & (T - 1);
+        fft.istride = 1;
+        fft.pad = true;
+        fft.init(lnj, tl, lds + slot * (nj + (nj >> kPadShift)));
+    } else {
+        slot = tid & (G - 1);
+        tl = tid >> lG;
+        fft.istride = G;
+        fft.pad = false;
+        fft.init(lnj, tl, lds + slot);
+    }
+
+    const int64_t estride = (axis == 0) ? 1 : ((int64_t)1 << lstride);
+    const double invN = 1.0 / (double)nj;
+    double2 kf[P];
+    int kf_inst = -1;
+
+    for (int64_t gg = blockIdx.x; gg < (int64_t)n_inst * gpi; gg += gridDim.x) {
+        const int inst = (int)(gg / gpi);
+        const int64_t g = gg - (int64_t)inst * gpi;
+        const InstDev &I = insts[inst];
+        const Rec &r = rec[((size_t)inst * rec_steps + step) * m + stage];
+        if (inst != kf_inst) {
+            const double gk = r.g[axis], ks = I.kscale[axis];
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                int q = tl + c * T;
+                int sq = q - ((q >= (nj >> 1)) ? nj : 0);
+                double k = ks * (double)sq;
+                double2 f = cis_neg(gk * (0.5 * k * k));
+                kf[c] = make_double2(f.x * invN, f.y * invN);
+            }
+            kf_inst = inst;
+        }
+        int64_t base;
+        if (axis == 0) {
+            base = ((g << lG) + slot) << lnj;
+        } else {
+            const int64_t ipo = ((int64_t)1 << lstride) >> lG;  // groups per outer index
+            const int64_t inner = (g % ipo) * G + slot;
+            const int64_t outer = g / ipo;
+            base = outer * ((int64_t)nj << lstride) + inner;
+        }
+        Store *u0 = psi + I.offset;
+        double2 u[P];
+#pragma unroll
+        for (int c = 0; c < P; ++c)
+            u[c] = to_d2(u0[base + (int64_t)(tl + c * T) * estride]);
+
+        auto xphase = [&](const Rec &q) {
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                const int64_t lin = base + (int64_t)(tl + c * T) * estride;
+                double th = 0.0, v = I.eps;
+                int shift = 0;
+                for (int j = 0; j < sh.ndim; ++j) {
+                    int i = (int)((lin >> shift) & (sh.n[j] - 1));
+                    shift += sh.logn[j];
+                    double x = I.lo[j] + (double)i * I.dx[j];
+                    th = fma(q.chi[j], 0.5 * x * x, th);
+                    v *= vtab[((size_t)inst * 3 + j) * vtab_stride + i];
+                }
+                double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
+                th = fma(q.w, v, fma(q.s, a2, th));
+                u[c] = cmul(u[c], cis_neg(th));
+            }
+        };
+
+        if (apply_open) xphase(rec_open[inst]);
+        fft.template run<-1>(u);
+#pragma unroll
+        for (int c = 0; c < P; ++c) u[c] = cmul(u[c], kf[c]);
+        fft.template run<+1>(u);
+        if (apply_close) xphase(r);
+#pragma unroll
+        for (int c = 0; c < P; ++c) u0[base + (int64_t)(tl + c * T) * estride] = from_d2<Store>(u[c]);
+    }
+}
+
+// Kinetic-energy partial sums along one axis: for every pencil along `axis`,
+// sum_k k_j^2 |FFT_j(u)|^2 / N_j; block b of instance k writes part[k*nblk + b].
+template <typename Store, int P, int MAXS>
+__global__ __launch_bounds__(kThreadsND) void kin_nd_kernel(const InstDev *__restrict__ insts, int nblk,
+                                                            const Store *__restrict__ psi, NdShape sh, int axis,
+                                                            double *__restrict__ part)
+{
+    constexpr int LOGP = Log2<P>::value;
+    constexpr int LDS_ELEMS = kThreadsND * P + ((kThreadsND * P) >> kPadShift);
+    __shared__ double2 lds[LDS_ELEMS];
+    __shared__ double red[2][kThreadsND];
+    const int inst = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    const InstDev &I = insts[inst];
+    const int lnj = sh.logn[axis], nj = 1 << lnj;
+    const int logT = lnj - LOGP, T = 1 << logT;
+    const int ltot = sh.logn[0] + sh.logn[1] + sh.logn[2];
+    const int64_t npencil = (int64_t)1 << (ltot - lnj);
+    int lG = 8 - logT;
+    if ((int64_t)1 << lG > npencil) lG = ltot - lnj;
+    const int G = 1 << lG;
+    const int tid = threadIdx.x;
+    const int slot = tid >> logT, tl = tid & (T - 1);
+    const bool active = slot < G;
+    int lstride = 0;
+    for (int j = 0; j < axis; ++j) lstride += sh.logn[j];
+    Fft1D<double2, P, MAXS> fft;
+    fft.init(lnj, tl, lds + slot * (nj + (nj >> kPadShift)));
+    double s = 0.0, cc = 0.0;
+    const Store *u0 = psi + I.offset;
+    for (int64_t g = blk; g < (npencil >> lG); g += nblk) {
+        const int64_t p = (g << lG) + slot;  // pencil index: (outer, inner) flattened
+        const int64_t inner = p & (((int64_t)1 << lstride) - 1), outer = p >> lstride;
+        const int64_t base = outer * ((int64_t)nj << lstride) + inner;
+        double2 u[P];
+#pragma unroll
+        for (int c = 0; c < P; ++c)
+            u[c] = active ? to_d2(u0[base + ((int64_t)(tl + c * T) << lstride)]) : make_double2(0.0, 0.0);
+        fft.template run<-1>(u);
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+            int q = tl + c * T;
+            int sq = q - ((q >= (nj >> 1)) ? nj : 0);
+            double k = I.kscale[axis] * (double)sq;
+            double v = k * k * fma(u[c].x, u[c].x, u[c].y * u[c].y) / (double)nj;
+            double t = s + v;
+            cc += (fabs(s) >= fabs(v)) ? ((s - t) + v) : ((v - t) + s);
+            s = t;
+        }
+        __syncthreads();
+    }
+    red[0][tid] = s;
+    red[1][tid] = cc;
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0, ac = 0.0;
+        for (int i = 0; i < kThreadsND; ++i) {
+            double v = red[0][i] + red[1][i];
+            double t = a + v;
+            ac += (fabs(a) >= fabs(v)) ? ((a - t) + v) : ((v - t) + a);
+            a = t;
+        }
+        part[(int64_t)inst * nblk + blk] = a + ac;
+    }
+}
+
+static NdShape make_shape(const LaunchND &L)
+{
+    NdShape sh;
+    sh.ndim = L.ndim;
+    for (int j = 0; j < 3; ++j) {
+        sh.n[j] = L.n[j];
+        sh.logn[j] = 0;
+        while ((1 << sh.logn[j]) < L.n[j]) ++sh.logn[j];
+    }
+    return sh;
+}
+
+// log2 of the pencils per group of an axis pass: 256/T pencils, limited by the
+// pencils available (x) or by the contiguous run of x positions (strided axes).
+int nd_group_log(const int *n, int axis)
+{
+    int logn[3], ltot = 0, lstride = 0;
+    for (int j = 0; j < 3; ++j) {
+        logn[j] = 0;
+        while ((1 << logn[j]) < n[j]) ++logn[j];
+        ltot += logn[j];
+        if (j < axis) lstride += logn[j];
+    }
+    int P = points_per_thread_nd(n[axis]);
+    int lp = 0;
+    while ((1 << lp) < P) ++lp;
+    int logT = logn[axis] - lp;
+    int lG = 8 - logT;
+    if (axis == 0) {
+        if (lG > ltot - logn[axis]) lG = ltot - logn[axis];
+    } else if (lG > lstride) {
+        lG = lstride;
+    }
+    return lG;
+}
+
+template <typename Store, int P, int MAXS>
+static hipError_t launch_pass_p(const LaunchND &L)
+{
+    NdShape sh = make_shape(L);
+    int lG = nd_group_log(L.n, L.axis);
+    int threads = 1 << (lG + sh.logn[L.axis] - Log2<P>::value);
+    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS>), dim3(L.grid), dim3(threads), 0, L.stream, L.insts,
+                       L.n_inst, L.rec, L.rec_open, L.vtab, L.vtab_stride, (Store *)L.psi, sh, L.axis, lG,
+                       L.stage, L.m, L.rec_steps, L.step, L.apply_open, L.apply_close);
+    return hipGetLastError();
+}
+
+template <typename Store>
+static hipError_t launch_pass_store(const LaunchND &L)
+{
+    switch (points_per_thread_nd(L.n[L.axis])) {
+    case 1: return launch_pass_p<Store, 1, 1>(L);
+    case 2: return launch_pass_p<Store, 2, 1>(L);
+    case 4: return launch_pass_p<Store, 4, 1>(L);
+    case 8: return launch_pass_p<Store, 8, 4>(L);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_nd_pass(const LaunchND &L)
+{
+    if (L.n_inst <= 0) return hipSuccess;
+    return L.c64 ? launch_pass_store<float2>(L) : launch_pass_store<double2>(L);
+}
+
+template <typename Store, int P, int MAXS>
+static hipError_t launch_kin_p(const LaunchND &L, int nblk, double *part)
+{
+    hipLaunchKernelGGL((kin_nd_kernel<Store, P, MAXS>), dim3(L.n_inst * nblk), dim3(kThreadsND), 0, L.stream,
+                       L.insts, nblk, (const Store *)L.psi, make_shape(L), L.axis, part);
+    return hipGetLastError();
+}
+
+template <typename Store>
+static hipError_t launch_kin_store(const LaunchND &L, int nblk, double *part)
+{
+    switch (points_per_thread_nd(L.n[L.axis])) {
+    case 1: return launch_kin_p<Store, 1, 1>(L, nblk, part);
+    case 2: return launch_kin_p<Store, 2, 1>(L, nblk, part);
+    case 4: return launch_kin_p<Store, 4, 1>(L, nblk, part);
+    case 8: return launch_kin_p<Store, 8, 4>(L, nblk, part);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_kinetic_nd(const LaunchND &L, int nblk, double *part)
+{
+    if (L.n_inst <= 0) return hipSuccess;
+    return L.c64 ? launch_kin_store<float2>(L, nblk, part) : launch_kin_store<double2>(L, nblk, part);
+}
+
+int points_per_thread_nd(int n)
+{
+    if (n <= 1) return 1;
+    if (n <= 4) return n;
+    if (n <= 2048) return 8;
+    return 0;
+}
+
+}  // namespace hfgpe

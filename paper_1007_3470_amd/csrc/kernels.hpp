@@ -75,4 +75,28 @@ struct LaunchKin1D {
 };
 hipError_t launch_kinetic_1d(const LaunchKin1D &L);
 
+// ---- d-D axis passes (kern_nd.hip) ----------------------------------------
+// All instances of a d-D plan share the grid shape n[].
+struct LaunchND {
+    const InstDev *insts;
+    int n_inst;
+    const Rec *rec;
+    const Rec *rec_open;
+    const double *vtab;  // [n_inst][3][vtab_stride]: V_I factor of each axis on its grid
+    int vtab_stride;
+    void *psi;
+    int c64;
+    int ndim;
+    int n[3];
+    int axis, stage, m, rec_steps, step;
+    int apply_open, apply_close;
+    int grid;  // persistent workgroups
+    hipStream_t stream;
+};
+hipError_t launch_nd_pass(const LaunchND &L);
+// Kinetic energy partials along L.axis: part[inst * nblk + b].
+hipError_t launch_kinetic_nd(const LaunchND &L, int nblk, double *part);
+int points_per_thread_nd(int n);
+int nd_group_log(const int *n, int axis);
+
 }  // namespace hfgpe

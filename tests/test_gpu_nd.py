@@ -1,0 +1,148 @@
+"""GPU parity of the 2-D / 3-D axis-pass HIP path against the CPU oracle."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-11, "c64": 5e-5}
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1007_3470_amd as p
+    p.load()
+    return p
+
+
+def run_gpu(pkg, w, dtype, nsteps=None, **kw):
+    import torch
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, **kw)
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, w.t0, w.nsteps if nsteps is None else nsteps)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    return plan, buf, plan.unpack(buf)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def reshape_workload(w, n, lo, hi):
+    """Same physics on another grid shape; fresh Gaussian initial data."""
+    insts, psis = [], []
+    for k, inst in enumerate(w.instances):
+        i2 = replace(inst, n=n, lo=lo, hi=hi)
+        mesh = i2.mesh()
+        r2 = sum((1.0 + 0.2 * j) * (m - 0.1 * k) ** 2 for j, m in enumerate(mesh))
+        insts.append(i2)
+        psis.append(W._normalise(i2, np.exp(-r2 / 2).astype(complex)))
+    return replace(w, instances=insts, psi0=psis)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_2d_small_batch(pkg, dtype):
+    w = W.gpe_2d(n=64, n_inst=3, nsteps=30)
+    _, _, got = run_gpu(pkg, w, dtype)
+    for k, inst in enumerate(w.instances):
+        ref = oracle.evolve(inst, w.psi0[k], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
+        err = W.rel_l2(got[k], ref)
+        say("2d %s k=%d rel_l2 %.3e" % (dtype, k, err))
+        assert err < TOL[dtype]
+
+
+@pytest.mark.parametrize("shape", [(128, 32, 1), (8, 256, 1), (2, 8, 1), (64, 2, 1)])
+def test_2d_anisotropic_shapes(pkg, shape):
+    w = reshape_workload(W.gpe_2d(n=8, n_inst=2, nsteps=12), shape, (-6.0, -5.0, 0.0), (7.0, 5.0, 1.0))
+    _, _, got = run_gpu(pkg, w, "c128")
+    for k, inst in enumerate(w.instances):
+        ref = oracle.evolve(inst, w.psi0[k], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
+        err = W.rel_l2(got[k], ref)
+        say("2d shape %s k=%d rel_l2 %.3e" % (shape, k, err))
+        assert err < 1e-11
+
+
+@pytest.mark.parametrize("scheme,rule", [("ni5_84", "cf4"), ("srkn6_4", "magnus6"), ("leapfrog", "cf4")])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_3d_small(pkg, scheme, rule, dtype):
+    w = W.gpe_3d(n=32, nsteps=6, scheme=scheme, rule=rule)
+    _, _, got = run_gpu(pkg, w, dtype)
+    ref = oracle.evolve(w.instances[0], w.psi0[0], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
+    err = W.rel_l2(got[0], ref)
+    say("3d %s %s %s rel_l2 %.3e" % (scheme, rule, dtype, err))
+    assert err < TOL[dtype]
+
+
+@pytest.mark.parametrize("shape", [(16, 64, 8), (4, 2, 32), (64, 16, 128)])
+def test_3d_anisotropic_shapes(pkg, shape):
+    base = W.gpe_3d(n=8, nsteps=5)
+    w = reshape_workload(replace(base, instances=base.instances * 2, psi0=base.psi0 * 2), shape,
+                         (-5.0, -6.0, -4.0), (5.0, 6.0, 4.5))
+    _, _, got = run_gpu(pkg, w, "c128")
+    for k, inst in enumerate(w.instances):
+        ref = oracle.evolve(inst, w.psi0[k], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
+        err = W.rel_l2(got[k], ref)
+        say("3d shape %s k=%d rel_l2 %.3e" % (shape, k, err))
+        assert err < 1e-11
+
+
+def test_nd_batch_vs_alone_bitwise(pkg):
+    w = W.gpe_2d(n=64, n_inst=4, nsteps=10)
+    _, _, a = run_gpu(pkg, w, "c128")
+    _, _, b = run_gpu(pkg, W.subset(w, [2]), "c128")
+    assert np.array_equal(a[2], b[0])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_nd_norm_energy(pkg, dtype):
+    for w in (W.gpe_2d(n=64, n_inst=2, nsteps=8), W.gpe_3d(n=32, nsteps=3)):
+        plan, buf, got = run_gpu(pkg, w, dtype)
+        t = w.t0 + w.nsteps * w.dt
+        nrm, en = plan.norm(buf), plan.energy(buf, t)
+        for k, inst in enumerate(w.instances):
+            assert abs(nrm[k] - oracle.norm(inst, got[k])) < 1e-12 * max(1, abs(nrm[k]))
+            ref = oracle.energy(inst, got[k], t)
+            assert np.allclose(en[k], ref, rtol=1e-11, atol=1e-11), (en[k], ref)
+
+
+# ---------------------------------------------------------------------------
+# full sizes, in the launch configuration of the solver
+# ---------------------------------------------------------------------------
+def test_2d_full_size(pkg):
+    w = W.gpe_2d()   # 16 x 512^2, 2000 steps
+    # sampled parity: the full batch for 60 steps, instance 5 against the oracle
+    _, _, short = run_gpu(pkg, w, "c128", nsteps=60)
+    ref = oracle.evolve(w.instances[5], w.psi0[5], w.scheme, w.ho_rule, w.dt, w.t0, 60)
+    err = W.rel_l2(short[5], ref)
+    say("2d full size, 60 steps, instance 5 vs oracle: %.3e" % err)
+    assert err < 1e-11
+    # the full run: norm conservation and c64 against c128
+    p128, b128, full128 = run_gpu(pkg, w, "c128")
+    p64, b64, full64 = run_gpu(pkg, w, "c64")
+    n0 = np.array([oracle.norm(i, p) for i, p in zip(w.instances, w.psi0)])
+    drift = np.abs(p128.norm(b128) - n0).max()
+    e64 = max(W.rel_l2(a, b) for a, b in zip(full64, full128))
+    say("2d full size 2000 steps: c128 norm drift %.3e, c64 vs c128 max %.3e" % (drift, e64))
+    assert drift < 1e-11 and e64 < 5e-5
+
+
+def test_3d_full_size(pkg):
+    w = W.gpe_3d()   # 256^3, NI5 + CF4, 500 steps
+    _, _, one = run_gpu(pkg, w, "c128", nsteps=1)
+    ref = oracle.evolve(w.instances[0], w.psi0[0], w.scheme, w.ho_rule, w.dt, w.t0, 1)
+    err = W.rel_l2(one[0], ref)
+    say("3d full size, 1 step vs oracle: %.3e" % err)
+    assert err < 1e-11
+    p128, b128, full128 = run_gpu(pkg, w, "c128")
+    p64, b64, full64 = run_gpu(pkg, w, "c64")
+    drift = abs(p128.norm(b128)[0] - oracle.norm(w.instances[0], w.psi0[0]))
+    e64 = W.rel_l2(full64[0], full128[0])
+    say("3d full size 500 steps: c128 norm drift %.3e, c64 vs c128 %.3e" % (drift, e64))
+    assert drift < 1e-11 and e64 < 5e-5
