@@ -1,5 +1,11 @@
 // devmath.hpp -- FP64 complex arithmetic, the phase factor exp(-i theta) and
 // in-register radix-2^k DFT butterflies for the gfx950 kernels.
+//
+// Every constant that multiplies data (sqrt(1/2), cos/sin(pi/8), the phase
+// table) enters as a hi + lo pair: a single rounded constant is biased in
+// magnitude by up to half an ulp, and a bias that repeats every step grows
+// linearly over thousands of steps (a rounded sqrt(1/2) alone drove a 2e-12
+// norm drift over 10^4 steps).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -22,53 +28,43 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b)
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
 // ---------------------------------------------------------------------------
-// exp(-i theta) in FP64, accurate to a few ulp for |theta| < 2^30.
-// Cody-Waite reduction by pi/2 with a two-word constant and FMA, then the
-// Taylor series of sin and cos on [-pi/4, pi/4] (sin through x^17, cos
-// through x^18, so the one-signed truncation error stays below 1e-19 and
-// |exp(-i theta)| carries no systematic bias), then the quadrant rotation.
+// exp(-i theta) with a 64-entry table: theta = n pi/32 + r, |r| <= pi/64,
+// exp(-i theta) = T[n mod 64] exp(-i r), T[j] = exp(-i j pi/32) held as a
+// hi + lo pair (tab[j], tab[64 + j]) so the product is rounded once and
+// carries no magnitude bias; short Taylor series for r (sin through r^9, cos
+// through r^10: truncation < 1e-20).  Roughly 60% of cis_neg's operations.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double2 cis_neg(double theta)
+constexpr int kCisTable = 64;
+
+__device__ __forceinline__ double2 cis_neg_tab(double theta, const double2 *__restrict__ tab)
 {
-    const double TWO_OVER_PI = 0.6366197723675814;
-    const double PIO2_HI = 1.5707963267948966;     // 0x1.921fb54442d18p+0
-    const double PIO2_LO = 6.123233995736766e-17;  // pi/2 - PIO2_HI
-    double n = rint(theta * TWO_OVER_PI);
-    double r = fma(-n, PIO2_HI, theta);
-    r = fma(-n, PIO2_LO, r);
+    const double K32 = 10.185916357881302;        // 32 / pi
+    const double C_HI = 0.09817477042468103;      // pi/32 (leading word)
+    const double C_LO = 3.827021247335479e-18;    // pi/32 - C_HI
+    double n = rint(theta * K32);
+    double r = fma(-n, C_HI, theta);
+    r = fma(-n, C_LO, r);
     double r2 = r * r;
-    // sin r = r - r^3/3! + r^5 (1/5! + r^2 (-1/7! + ...)); 1/3! and 1/4! enter as
-    // hi + lo pairs (their rounding would otherwise bias |exp(-i theta)|)
-    double ps = 2.8114572543455206e-15;         //  1/17!
-    ps = fma(ps, r2, -7.647163731819816e-13);   // -1/15!
-    ps = fma(ps, r2, 1.6059043836821613e-10);   //  1/13!
-    ps = fma(ps, r2, -2.505210838544172e-08);   // -1/11!
-    ps = fma(ps, r2, 2.7557319223985893e-06);   //  1/9!
-    ps = fma(ps, r2, -1.984126984126984e-04);   // -1/7!
-    ps = fma(ps, r2, 8.333333333333333e-03);    //  1/5!
-    double r3 = r * r2;
-    double st = fma(r3, -9.251858538542971e-18, r3 * r2 * ps);
-    double s = r + fma(r3, -1.6666666666666666e-01, st);
-    // cos r = 1 - r^2/2 + r^4/4! + r^6 (-1/6! + r^2 (1/8! + ...))
-    double pc = -1.5619206968586225e-16;        // -1/18!
-    pc = fma(pc, r2, 4.779477332387385e-14);    //  1/16!
-    pc = fma(pc, r2, -1.1470745597729725e-11);  // -1/14!
-    pc = fma(pc, r2, 2.08767569878681e-09);     //  1/12!
-    pc = fma(pc, r2, -2.755731922398589e-07);   // -1/10!
-    pc = fma(pc, r2, 2.48015873015873e-05);     //  1/8!
-    pc = fma(pc, r2, -1.3888888888888889e-03);  // -1/6!
-    double r4 = r2 * r2;
-    double ct = fma(r4, 2.3129646346357427e-18, r4 * r2 * pc);
+    double ps = fma(r2, 2.7557319223985893e-06, -1.984126984126984e-04);  // 1/9!, -1/7!
+    ps = fma(ps, r2, 8.333333333333333e-03);                               // 1/5!
+    ps = fma(ps, r2, -1.6666666666666666e-01);                             // -1/3!
+    double s = fma(r * r2, ps, r);
+    double pc = fma(r2, 2.755731922398589e-07, -2.48015873015873e-05);    // 1/10!, -1/8!
+    pc = fma(pc, r2, 1.3888888888888889e-03);                              // 1/6!
+    pc = fma(pc, r2, -4.1666666666666664e-02);                             // -1/4!
     double hr = 0.5 * r2;
     double w = 1.0 - hr;
-    double c = w + (((1.0 - w) - hr) + fma(r4, 4.1666666666666664e-02, ct));
-    // theta = n pi/2 + r: rotate (cos r, sin r) by the quadrant
-    int q = ((int)n) & 3;
-    double cq = (q & 1) ? s : c;
-    double sq = (q & 1) ? c : s;
-    if (q == 1 || q == 2) cq = -cq;
-    if (q >= 2) sq = -sq;
-    return make_double2(cq, -sq);
+    double c = w + (((1.0 - w) - hr) - r2 * r2 * pc);
+    const int j = ((int)n) & (kCisTable - 1);
+    const double2 th = tab[j], tl = tab[kCisTable + j];
+    // (th + tl) (c - i s)
+    return make_double2(fma(th.x, c, fma(th.y, s, fma(tl.x, c, tl.y * s))),
+                        fma(th.y, c, fma(-th.x, s, fma(tl.y, c, -tl.x * s))));
+}
+
+__device__ __forceinline__ void load_cis_table(double2 *lds_tab, const double2 *__restrict__ gtab)
+{
+    for (int j = threadIdx.x; j < 2 * kCisTable; j += blockDim.x) lds_tab[j] = gtab[j];
 }
 
 // ---------------------------------------------------------------------------

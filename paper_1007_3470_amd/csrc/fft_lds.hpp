@@ -16,7 +16,10 @@
 namespace hfgpe {
 
 constexpr int kThreads1D = 256;
-constexpr int kPadShift = 4;  // one padding element every 16 in LDS
+#ifndef HFGPE_PAD_SHIFT
+#define HFGPE_PAD_SHIFT 3
+#endif
+constexpr int kPadShift = HFGPE_PAD_SHIFT;  // one padding element every 2^kPadShift in LDS
 
 __device__ __forceinline__ int lds_pad(int idx) { return idx + (idx >> kPadShift); }
 
@@ -50,7 +53,11 @@ struct Fft1D {
 
     int logn, logT, S, r0log, tl;
     Xch *buf;
-    double2 tw[NTW][PW];
+    // Twiddles of passes 1..S-1: for radix 8 only w^1, w^2, w^4 are kept and
+    // the rest formed by products when a pass runs (fewer registers); other
+    // radices keep all P-1 powers.
+    static constexpr int NKEEP = (P == 8) ? 3 : PW;
+    double2 tw[NTW][NKEEP];
 
     __device__ void init(int logn_, int tl_, Xch *buf_)
     {
@@ -68,13 +75,33 @@ struct Fft1D {
                 int k = tl & ((1 << logL) - 1);
                 int slog = logn - logL - LOGP;
 #pragma unroll
-                for (int r = 1; r < P; ++r) {
+                for (int q = 0; q < NKEEP; ++q) {
+                    int r = (P == 8) ? (1 << q) : q + 1;
                     int e = (r * k) << slog;
                     double sn, cs;
                     sincospi(-2.0 * (double)e * invN, &sn, &cs);
-                    tw[s - 1][r - 1] = make_double2(cs, sn);
+                    tw[s - 1][q] = make_double2(cs, sn);
                 }
             }
+        }
+    }
+
+    // twiddle r (1..P-1) of pass s
+    __device__ __forceinline__ void twiddles(int s, double2 *w) const
+    {
+        if constexpr (P == 8) {
+            const double2 w1 = tw[s - 1][0], w2 = tw[s - 1][1], w4 = tw[s - 1][2];
+            const double2 w3 = cmul(w1, w2);
+            w[0] = w1;
+            w[1] = w2;
+            w[2] = w3;
+            w[3] = w4;
+            w[4] = cmul(w1, w4);
+            w[5] = cmul(w2, w4);
+            w[6] = cmul(w3, w4);
+        } else {
+#pragma unroll
+            for (int r = 0; r < PW; ++r) w[r] = tw[s - 1][r];
         }
     }
 
@@ -120,9 +147,10 @@ struct Fft1D {
 #pragma unroll
                     for (int c = 0; c < P; ++c) u[c] = to_d2(buf[map(tl + c * T)]);
                     __syncthreads();
+                    double2 w[PW];
+                    twiddles(s, w);
 #pragma unroll
-                    for (int r = 1; r < P; ++r)
-                        u[r] = (SGN < 0) ? cmul(u[r], tw[s - 1][r - 1]) : cmulc(u[r], tw[s - 1][r - 1]);
+                    for (int r = 1; r < P; ++r) u[r] = (SGN < 0) ? cmul(u[r], w[r - 1]) : cmulc(u[r], w[r - 1]);
                     Dft<P, SGN>::run(u);
                     if (s < S - 1) {
                         int logL = r0log + LOGP * (s - 1);

@@ -11,6 +11,7 @@
 
 #include "../../include/hfgpe.h"
 #include "coeff.hpp"
+#include "devmath.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 
@@ -75,6 +76,7 @@ struct hfgpe_plan {
     double *d_part = nullptr;
     double *d_kin = nullptr;
     int nblk = 1;
+    double2 *d_cistab = nullptr;  // exp(-i j pi/32), j < 64, hi then lo words
     double *d_vtab = nullptr;  // d-D: V_I factor per axis on its grid
     int vtab_stride = 0;
     double *d_kpart = nullptr;  // d-D kinetic-energy partials
@@ -96,6 +98,7 @@ struct hfgpe_plan {
         if (d_part) (void)hipFree(d_part);
         if (d_kin) (void)hipFree(d_kin);
         if (d_vtab) (void)hipFree(d_vtab);
+        if (d_cistab) (void)hipFree(d_cistab);
         if (d_kpart) (void)hipFree(d_kpart);
         for (auto *v : {&ev_step, &ev_coeff, &ev_pool})
             for (auto &e : *v) {
@@ -436,6 +439,21 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
     ALLOC_TRY(P->d_rec, sizeof(Rec) * (size_t)n_inst * S.m * P->rec_steps_cap);
     ALLOC_TRY(P->d_part, sizeof(double) * 4 * (size_t)n_inst * P->nblk);
     ALLOC_TRY(P->d_kin, sizeof(double) * n_inst);
+    {
+        // phase-factor table: exp(-i j pi/32) split into hi + lo words, evaluated
+        // in extended precision on the host
+        std::vector<double2> tab(2 * kCisTable);
+        const long double pi = 3.14159265358979323846264338327950288L;
+        for (int j = 0; j < kCisTable; ++j) {
+            long double a = (long double)j * pi / 32.0L;
+            long double c = cosl(a), s = -sinl(a);
+            double ch = (double)c, sh = (double)s;
+            tab[j] = make_double2(ch, sh);
+            tab[kCisTable + j] = make_double2((double)(c - (long double)ch), (double)(s - (long double)sh));
+        }
+        ALLOC_TRY(P->d_cistab, sizeof(double2) * tab.size());
+        COPY_TRY(P->d_cistab, tab.data(), sizeof(double2) * tab.size());
+    }
     for (auto &g : P->groups) {
         ALLOC_TRY(g.d_items, sizeof(Item1D) * g.items.size());
         COPY_TRY(g.d_items, g.items.data(), sizeof(Item1D) * g.items.size());
@@ -528,6 +546,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
                         L.rec_open = P->d_rec_open;
                         L.vtab = P->d_vtab;
                         L.vtab_stride = P->vtab_stride;
+                        L.cistab = P->d_cistab;
                         L.psi = d_psi;
                         L.c64 = P->dtype == HFGPE_C64;
                         L.ndim = P->ndim;
@@ -566,6 +585,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
                 L.insts = P->d_insts;
                 L.rec = P->d_rec;
                 L.rec_open = P->d_rec_open;
+                L.cistab = P->d_cistab;
                 L.psi = d_psi;
                 L.m = m;
                 L.K = kk;

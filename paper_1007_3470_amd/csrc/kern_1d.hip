@@ -26,11 +26,12 @@
 namespace hfgpe {
 
 template <typename Store, typename Xch, int P, int MAXS>
-__global__ __launch_bounds__(kThreads1D) void hf1d_kernel(const Item1D *__restrict__ items,
+__global__ __launch_bounds__(kThreads1D, 2) void hf1d_kernel(const Item1D *__restrict__ items,
                                                           const int *__restrict__ perm,
                                                           const InstDev *__restrict__ insts,
                                                           const Rec *__restrict__ rec,
                                                           const Rec *__restrict__ rec_open,
+                                                          const double2 *__restrict__ cistab,
                                                           Store *__restrict__ psi, int m, int K,
                                                           int rec_steps, int step_base,
                                                           int apply_opening)
@@ -38,6 +39,9 @@ __global__ __launch_bounds__(kThreads1D) void hf1d_kernel(const Item1D *__restri
     constexpr int LOGP = Log2<P>::value;
     constexpr int LDS_ELEMS = kThreads1D * P + ((kThreads1D * P) >> kPadShift);
     __shared__ Xch lds[LDS_ELEMS];
+    __shared__ double2 ctab[2 * kCisTable];
+    __shared__ double vel[kThreads1D * P];  // eps V_I at every point of the group
+    load_cis_table(ctab, cistab);
 
     const Item1D it = items[blockIdx.x];
     const int logn = it.logn;
@@ -55,26 +59,27 @@ __global__ __launch_bounds__(kThreads1D) void hf1d_kernel(const Item1D *__restri
     fft.init(logn, tl, lds + slot * (N + (N >> kPadShift)));
 
     double2 u[P];
-    double x2h[P], ve[P];
     const double lo = I.lo[0], dx = I.dx[0], eps = I.eps;
     const VFac vf = I.vf[0];
     Store *base = psi + I.offset;
+    double *ve = vel + slot * N;
 #pragma unroll
     for (int c = 0; c < P; ++c) {
         int i = tl + c * T;
         double x = lo + (double)i * dx;
-        x2h[c] = 0.5 * x * x;
-        ve[c] = eps * vfactor(vf, x);
+        ve[i] = eps * vfactor(vf, x);
         u[c] = active ? to_d2(base[i]) : make_double2(0.0, 0.0);
     }
+    __syncthreads();  // cis table in LDS
 
     auto xphase = [&](const Rec &r) {
         const double chi = r.chi[0], w = r.w, s = r.s;
 #pragma unroll
         for (int c = 0; c < P; ++c) {
+            double x = lo + (double)(tl + c * T) * dx;
             double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
-            double th = fma(chi, x2h[c], fma(w, ve[c], s * a2));
-            u[c] = cmul(u[c], cis_neg(th));
+            double th = fma(chi, 0.5 * x * x, fma(w, ve[tl + c * T], s * a2));
+            u[c] = cmul(u[c], cis_neg_tab(th, ctab));
         }
     };
 
@@ -92,7 +97,7 @@ __global__ __launch_bounds__(kThreads1D) void hf1d_kernel(const Item1D *__restri
                 int q = tl + c * T;
                 int sq = q - ((q >= (N >> 1)) ? N : 0);
                 double k = ks * (double)sq;
-                double2 f = cis_neg(g * (0.5 * k * k));
+                double2 f = cis_neg_tab(g * (0.5 * k * k), ctab);
                 u[c] = cmul(u[c], make_double2(f.x * invN, f.y * invN));
             }
             fft.template run<+1>(u);
@@ -197,7 +202,7 @@ template <typename Store, typename Xch, int P, int MAXS>
 static hipError_t launch_p(const Launch1D &L)
 {
     hipLaunchKernelGGL((hf1d_kernel<Store, Xch, P, MAXS>), dim3(L.n_items), dim3(kThreads1D), 0, L.stream,
-                       L.items, L.perm, L.insts, L.rec, L.rec_open, (Store *)L.psi, L.m, L.K, L.rec_steps,
+                       L.items, L.perm, L.insts, L.rec, L.rec_open, L.cistab, (Store *)L.psi, L.m, L.K, L.rec_steps,
                        L.step_base, L.apply_opening);
     return hipGetLastError();
 }

@@ -35,12 +35,15 @@ template <typename Store, int P, int MAXS>
 __global__ __launch_bounds__(kThreadsND) void hfnd_pass_kernel(
     const InstDev *__restrict__ insts, int n_inst, const Rec *__restrict__ rec,
     const Rec *__restrict__ rec_open, const double *__restrict__ vtab, int vtab_stride,
-    Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step,
+    const double2 *__restrict__ cistab, Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step,
     int apply_open, int apply_close)
 {
     constexpr int LOGP = Log2<P>::value;
     constexpr int LDS_ELEMS = kThreadsND * P + ((kThreadsND * P) >> kPadShift);
     __shared__ double2 lds[LDS_ELEMS];
+    __shared__ double2 ctab[2 * kCisTable];
+    load_cis_table(ctab, cistab);
+    __syncthreads();
 
     const int lnj = sh.logn[axis];
     const int nj = 1 << lnj;
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(kThreadsND) void hfnd_pass_kernel(
                 int q = tl + c * T;
                 int sq = q - ((q >= (nj >> 1)) ? nj : 0);
                 double k = ks * (double)sq;
-                double2 f = cis_neg(gk * (0.5 * k * k));
+                double2 f = cis_neg_tab(gk * (0.5 * k * k), ctab);
                 kf[c] = make_double2(f.x * invN, f.y * invN);
             }
             kf_inst = inst;
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(kThreadsND) void hfnd_pass_kernel(
                 }
                 double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
                 th = fma(q.w, v, fma(q.s, a2, th));
-                u[c] = cmul(u[c], cis_neg(th));
+                u[c] = cmul(u[c], cis_neg_tab(th, ctab));
             }
         };
 
@@ -245,7 +248,7 @@ static hipError_t launch_pass_p(const LaunchND &L)
     int lG = nd_group_log(L.n, L.axis);
     int threads = 1 << (lG + sh.logn[L.axis] - Log2<P>::value);
     hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS>), dim3(L.grid), dim3(threads), 0, L.stream, L.insts,
-                       L.n_inst, L.rec, L.rec_open, L.vtab, L.vtab_stride, (Store *)L.psi, sh, L.axis, lG,
+                       L.n_inst, L.rec, L.rec_open, L.vtab, L.vtab_stride, L.cistab, (Store *)L.psi, sh, L.axis, lG,
                        L.stage, L.m, L.rec_steps, L.step, L.apply_open, L.apply_close);
     return hipGetLastError();
 }

@@ -32,6 +32,7 @@ struct Launch1D {
     const InstDev *insts;
     const Rec *rec;
     const Rec *rec_open;
+    const double2 *cistab;  // 2 x 64 entries: exp(-i j pi/32) as hi, lo
     void *psi;
     int m;
     int K;            // steps advanced by this launch
@@ -84,6 +85,7 @@ struct LaunchND {
     const Rec *rec_open;
     const double *vtab;  // [n_inst][3][vtab_stride]: V_I factor of each axis on its grid
     int vtab_stride;
+    const double2 *cistab;
     void *psi;
     int c64;
     int ndim;
