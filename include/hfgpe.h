@@ -119,6 +119,7 @@ typedef struct {
     int use_graph;         /* 1 = replay chunks from a captured hipGraph */
     int profile;           /* 1 = bracket every step-kernel launch with HIP
                               events on the plan's stream (hfgpe_profile) */
+    int nd_workgroups;     /* d-D: persistent workgroups per axis pass (0 = auto) */
 } hfgpe_options;
 
 typedef struct hfgpe_plan hfgpe_plan;

@@ -59,7 +59,9 @@ struct Fft1D {
     static constexpr int NKEEP = (P == 8) ? 3 : PW;
     double2 tw[NTW][NKEEP];
 
-    __device__ void init(int logn_, int tl_, Xch *buf_)
+    // twtab (optional): exp(-2 pi i q / 2^twlog) for q < 2^twlog, twlog >= logn
+    __device__ void init(int logn_, int tl_, Xch *buf_, const double2 *__restrict__ twtab = nullptr,
+                         int twlog = 0)
     {
         logn = logn_;
         tl = tl_;
@@ -78,9 +80,13 @@ struct Fft1D {
                 for (int q = 0; q < NKEEP; ++q) {
                     int r = (P == 8) ? (1 << q) : q + 1;
                     int e = (r * k) << slog;
-                    double sn, cs;
-                    sincospi(-2.0 * (double)e * invN, &sn, &cs);
-                    tw[s - 1][q] = make_double2(cs, sn);
+                    if (twtab) {
+                        tw[s - 1][q] = twtab[e << (twlog - logn)];
+                    } else {
+                        double sn, cs;
+                        sincospi(-2.0 * (double)e * invN, &sn, &cs);
+                        tw[s - 1][q] = make_double2(cs, sn);
+                    }
                 }
             }
         }

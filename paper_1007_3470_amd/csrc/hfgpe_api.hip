@@ -77,6 +77,8 @@ struct hfgpe_plan {
     double *d_kin = nullptr;
     int nblk = 1;
     double2 *d_cistab = nullptr;  // exp(-i j pi/32), j < 64, hi then lo words
+    double2 *d_twtab = nullptr;   // d-D: exp(-2 pi i q / 2^twlog)
+    int twlog = 0;
     double *d_vtab = nullptr;  // d-D: V_I factor per axis on its grid
     int vtab_stride = 0;
     double *d_kpart = nullptr;  // d-D kinetic-energy partials
@@ -99,6 +101,7 @@ struct hfgpe_plan {
         if (d_kin) (void)hipFree(d_kin);
         if (d_vtab) (void)hipFree(d_vtab);
         if (d_cistab) (void)hipFree(d_cistab);
+        if (d_twtab) (void)hipFree(d_twtab);
         if (d_kpart) (void)hipFree(d_kpart);
         for (auto *v : {&ev_step, &ev_coeff, &ev_pool})
             for (auto &e : *v) {
@@ -479,7 +482,21 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
             int lG = nd_group_log(P->insts[0].n, j);
             groups = std::max<int64_t>(groups, (int64_t)n_inst * ((pts / P->insts[0].n[j]) >> lG));
         }
-        P->nd_grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, 2048));
+        // persistent workgroups: a few per CU, each looping over many pencil groups
+        int want = P->opts.nd_workgroups > 0 ? P->opts.nd_workgroups : 512;
+        P->nd_grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, want));
+        // FFT twiddles for every axis length, evaluated in extended precision
+        int nmax = 1;
+        for (int j = 0; j < nd; ++j) nmax = std::max(nmax, P->insts[0].n[j]);
+        P->twlog = ilog2(nmax);
+        std::vector<double2> tw(nmax);
+        const long double pi = 3.14159265358979323846264338327950288L;
+        for (int q = 0; q < nmax; ++q) {
+            long double a = -2.0L * pi * (long double)q / (long double)nmax;
+            tw[q] = make_double2((double)cosl(a), (double)sinl(a));
+        }
+        ALLOC_TRY(P->d_twtab, sizeof(double2) * tw.size());
+        COPY_TRY(P->d_twtab, tw.data(), sizeof(double2) * tw.size());
     }
 #undef ALLOC_TRY
 #undef COPY_TRY
@@ -547,6 +564,8 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
                         L.vtab = P->d_vtab;
                         L.vtab_stride = P->vtab_stride;
                         L.cistab = P->d_cistab;
+                        L.twtab = P->d_twtab;
+                        L.twlog = P->twlog;
                         L.psi = d_psi;
                         L.c64 = P->dtype == HFGPE_C64;
                         L.ndim = P->ndim;

@@ -31,17 +31,21 @@ struct NdShape {
     int logn[3];
 };
 
-template <typename Store, int P, int MAXS>
-__global__ __launch_bounds__(kThreadsND) void hfnd_pass_kernel(
+// MODE: 0 = drift only, 1 = closing x-phase after the drift, 2 = opening
+// x-phase before it (separate instantiations keep unused phase code out of
+// the register allocation).
+template <typename Store, int P, int MAXS, int MODE>
+__global__ __launch_bounds__(kThreadsND, 2) void hfnd_pass_kernel(
     const InstDev *__restrict__ insts, int n_inst, const Rec *__restrict__ rec,
     const Rec *__restrict__ rec_open, const double *__restrict__ vtab, int vtab_stride,
-    const double2 *__restrict__ cistab, Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step,
-    int apply_open, int apply_close)
+    const double2 *__restrict__ cistab, const double2 *__restrict__ twtab, int twlog,
+    Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step)
 {
     constexpr int LOGP = Log2<P>::value;
     constexpr int LDS_ELEMS = kThreadsND * P + ((kThreadsND * P) >> kPadShift);
     __shared__ double2 lds[LDS_ELEMS];
     __shared__ double2 ctab[2 * kCisTable];
+    __shared__ double2 kfl[kThreadsND * P];  // drift factor of every wavenumber of the axis
     load_cis_table(ctab, cistab);
     __syncthreads();
 
@@ -64,79 +68,94 @@ __global__ __launch_bounds__(kThreadsND) void hfnd_pass_kernel(
         tl = tid & (T - 1);
         fft.istride = 1;
         fft.pad = true;
-        fft.init(lnj, tl, lds + slot * (nj + (nj >> kPadShift)));
+        fft.init(lnj, tl, lds + slot * (nj + (nj >> kPadShift)), twtab, twlog);
     } else {
         slot = tid & (G - 1);
         tl = tid >> lG;
         fft.istride = G;
         fft.pad = false;
-        fft.init(lnj, tl, lds + slot);
+        fft.init(lnj, tl, lds + slot, twtab, twlog);
     }
 
-    const int64_t estride = (axis == 0) ? 1 : ((int64_t)1 << lstride);
     const double invN = 1.0 / (double)nj;
-    double2 kf[P];
     int kf_inst = -1;
 
-    for (int64_t gg = blockIdx.x; gg < (int64_t)n_inst * gpi; gg += gridDim.x) {
+    // each workgroup takes a contiguous range of groups (the drift factors change
+    // only when the instance does; neighbouring pencils share cache lines)
+    const int64_t total = (int64_t)n_inst * gpi;
+    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+    const int64_t g_end = (blockIdx.x + 1) * per < total ? (blockIdx.x + 1) * per : total;
+    for (int64_t gg = blockIdx.x * per; gg < g_end; ++gg) {
         const int inst = (int)(gg / gpi);
         const int64_t g = gg - (int64_t)inst * gpi;
         const InstDev &I = insts[inst];
         const Rec &r = rec[((size_t)inst * rec_steps + step) * m + stage];
-        if (inst != kf_inst) {
+        if (inst != kf_inst) {  // uniform across the workgroup
             const double gk = r.g[axis], ks = I.kscale[axis];
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                int q = tl + c * T;
+            __syncthreads();
+            for (int q = threadIdx.x; q < nj; q += blockDim.x) {
                 int sq = q - ((q >= (nj >> 1)) ? nj : 0);
                 double k = ks * (double)sq;
                 double2 f = cis_neg_tab(gk * (0.5 * k * k), ctab);
-                kf[c] = make_double2(f.x * invN, f.y * invN);
+                kfl[q] = make_double2(f.x * invN, f.y * invN);
             }
+            __syncthreads();
             kf_inst = inst;
         }
-        int64_t base;
+        // first element of this thread's pencil (offsets within an instance fit in 32 bits)
+        int base;
         if (axis == 0) {
-            base = ((g << lG) + slot) << lnj;
+            base = (int)(((g << lG) + slot) << lnj);
         } else {
             const int64_t ipo = ((int64_t)1 << lstride) >> lG;  // groups per outer index
-            const int64_t inner = (g % ipo) * G + slot;
-            const int64_t outer = g / ipo;
-            base = outer * ((int64_t)nj << lstride) + inner;
+            const int inner = (int)((g % ipo) * G + slot);
+            const int outer = (int)(g / ipo);
+            base = outer * (nj << lstride) + inner;
         }
-        Store *u0 = psi + I.offset;
+        const int estr = (axis == 0) ? 1 : (1 << lstride);
+        Store *u0 = psi + I.offset + base;
         double2 u[P];
 #pragma unroll
-        for (int c = 0; c < P; ++c)
-            u[c] = to_d2(u0[base + (int64_t)(tl + c * T) * estride]);
+        for (int c = 0; c < P; ++c) u[c] = to_d2(u0[(tl + c * T) * estr]);
 
+        // merged x-phase: along a pencil only the pass axis's coordinate varies, so
+        // the other axes' chirp and V_I factors are formed once per pencil
         auto xphase = [&](const Rec &q) {
+            double th0 = 0.0, v0 = I.eps;
+            int shift = 0;
+            for (int j = 0; j < sh.ndim; ++j) {
+                if (j != axis) {
+                    int i = (base >> shift) & (sh.n[j] - 1);
+                    double x = I.lo[j] + (double)i * I.dx[j];
+                    th0 = fma(q.chi[j], 0.5 * x * x, th0);
+                    v0 *= vtab[((size_t)inst * 3 + j) * vtab_stride + i];
+                }
+                shift += sh.logn[j];
+            }
+            const double chia = q.chi[axis], loa = I.lo[axis], dxa = I.dx[axis];
+            const double *va = vtab + ((size_t)inst * 3 + axis) * vtab_stride;
+            const double wv0 = q.w * v0;
 #pragma unroll
             for (int c = 0; c < P; ++c) {
-                const int64_t lin = base + (int64_t)(tl + c * T) * estride;
-                double th = 0.0, v = I.eps;
-                int shift = 0;
-                for (int j = 0; j < sh.ndim; ++j) {
-                    int i = (int)((lin >> shift) & (sh.n[j] - 1));
-                    shift += sh.logn[j];
-                    double x = I.lo[j] + (double)i * I.dx[j];
-                    th = fma(q.chi[j], 0.5 * x * x, th);
-                    v *= vtab[((size_t)inst * 3 + j) * vtab_stride + i];
-                }
+                const int i = tl + c * T;
+                const double x = loa + (double)i * dxa;
                 double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
-                th = fma(q.w, v, fma(q.s, a2, th));
+                double th = fma(chia, 0.5 * x * x, fma(wv0, va[i], fma(q.s, a2, th0)));
                 u[c] = cmul(u[c], cis_neg_tab(th, ctab));
+                // keep the scheduler from interleaving all P phase evaluations
+                // (register pressure); pairs still overlap
+                if (c & 1) __builtin_amdgcn_sched_barrier(0);
             }
         };
 
-        if (apply_open) xphase(rec_open[inst]);
+        if constexpr (MODE == 2) xphase(rec_open[inst]);
         fft.template run<-1>(u);
 #pragma unroll
-        for (int c = 0; c < P; ++c) u[c] = cmul(u[c], kf[c]);
+        for (int c = 0; c < P; ++c) u[c] = cmul(u[c], kfl[tl + c * T]);
         fft.template run<+1>(u);
-        if (apply_close) xphase(r);
+        if constexpr (MODE == 1) xphase(r);
 #pragma unroll
-        for (int c = 0; c < P; ++c) u0[base + (int64_t)(tl + c * T) * estride] = from_d2<Store>(u[c]);
+        for (int c = 0; c < P; ++c) u0[(tl + c * T) * estr] = from_d2<Store>(u[c]);
     }
 }
 
@@ -241,16 +260,27 @@ int nd_group_log(const int *n, int axis)
     return lG;
 }
 
-template <typename Store, int P, int MAXS>
-static hipError_t launch_pass_p(const LaunchND &L)
+template <typename Store, int P, int MAXS, int MODE>
+static hipError_t launch_pass_mode(const LaunchND &L)
 {
     NdShape sh = make_shape(L);
     int lG = nd_group_log(L.n, L.axis);
     int threads = 1 << (lG + sh.logn[L.axis] - Log2<P>::value);
-    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS>), dim3(L.grid), dim3(threads), 0, L.stream, L.insts,
-                       L.n_inst, L.rec, L.rec_open, L.vtab, L.vtab_stride, L.cistab, (Store *)L.psi, sh, L.axis, lG,
-                       L.stage, L.m, L.rec_steps, L.step, L.apply_open, L.apply_close);
+    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE>), dim3(L.grid), dim3(threads), 0, L.stream, L.insts,
+                       L.n_inst, L.rec, L.rec_open, L.vtab, L.vtab_stride, L.cistab, L.twtab, L.twlog,
+                       (Store *)L.psi, sh, L.axis, lG, L.stage, L.m, L.rec_steps, L.step);
     return hipGetLastError();
+}
+
+template <typename Store, int P, int MAXS>
+static hipError_t launch_pass_p(const LaunchND &L)
+{
+    // an evolve call opens on the first x pass and closes every stage on the
+    // last axis; with d >= 2 these never fall on the same pass
+    if (L.apply_open && L.apply_close) return hipErrorInvalidValue;
+    if (L.apply_close) return launch_pass_mode<Store, P, MAXS, 1>(L);
+    if (L.apply_open) return launch_pass_mode<Store, P, MAXS, 2>(L);
+    return launch_pass_mode<Store, P, MAXS, 0>(L);
 }
 
 template <typename Store>

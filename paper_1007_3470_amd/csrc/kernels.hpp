@@ -86,6 +86,8 @@ struct LaunchND {
     const double *vtab;  // [n_inst][3][vtab_stride]: V_I factor of each axis on its grid
     int vtab_stride;
     const double2 *cistab;
+    const double2 *twtab;  // exp(-2 pi i q / 2^twlog), q < 2^twlog
+    int twlog;
     void *psi;
     int c64;
     int ndim;
