@@ -116,7 +116,10 @@ typedef struct {
                               the evolve call up to an internal cap) */
     int plain;             /* 1 = reference schedule: one launch per step per
                               grid-size group, no graphs */
-    int use_graph;         /* 1 = replay chunks from a captured hipGraph */
+    int use_graph;         /* 1 = d-D plans replay blocks of 16 steps from a
+                              captured hipGraph (a plan on the legacy default
+                              stream then runs on a blocking stream of its own,
+                              ordered against the default stream) */
     int profile;           /* 1 = bracket every step-kernel launch with HIP
                               events on the plan's stream (hfgpe_profile) */
     int nd_workgroups;     /* d-D: persistent workgroups per axis pass (0 = auto) */
@@ -180,6 +183,16 @@ int hfgpe_stage_coeffs_params(const hfgpe_params *params, int ndim, const hfgpe_
  * "ni4_82", "ni5_84" (Table tab.1).  Writes m into *m and, when a and b are
  * non-NULL, the coefficients (room for 16 and 17 doubles). */
 int hfgpe_scheme_preset(const char *name, int *m, double *a, double *b);
+
+/* Pick the plan's schedule by timing candidates with HIP events on its
+ * stream: for d-D plans the number of persistent workgroups per axis pass
+ * (256 ... 2048), for 1-D plans the steps per resident launch (whole chunk,
+ * 1024 or 256; candidates not shorter than trial_steps are skipped).  d_scratch is a device buffer
+ * of the plan's layout holding representative data (its contents are
+ * overwritten); trial_steps steps are run per candidate (>= 1).  The winning
+ * setting is kept in the plan and written to *choice (may be NULL).
+ * Synchronises the stream. */
+int hfgpe_autotune(hfgpe_plan *plan, void *d_scratch, int64_t trial_steps, int *choice);
 
 /* Device-side error word raised by the coefficient kernel since the last
  * call (0 or a status code); synchronises and clears it. */

@@ -28,7 +28,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "si
 SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", "hfgpe_evolve",
            "hfgpe_norm", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
            "hfgpe_scheme_preset",
-           "hfgpe_device_status", "hfgpe_profile", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
+           "hfgpe_device_status", "hfgpe_profile", "hfgpe_autotune", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
 
 
 class HfgpeError(RuntimeError):
@@ -94,6 +94,7 @@ def load() -> ctypes.CDLL:
     lib.hfgpe_scheme_preset.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), dp, dp]
     lib.hfgpe_device_status.argtypes = [vp]
     lib.hfgpe_profile.argtypes = [vp, dp, dp, i64p]
+    lib.hfgpe_autotune.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int)]
     lib.hfgpe_status_string.argtypes = [ctypes.c_int]
     lib.hfgpe_status_string.restype = ctypes.c_char_p
     lib.hfgpe_version.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -239,6 +240,15 @@ class Plan:
         _check(self.lib.hfgpe_profile(self.handle, ctypes.byref(sm), ctypes.byref(cm),
                                       ctypes.byref(n)), "hfgpe_profile")
         return sm.value, cm.value, n.value
+
+    def autotune(self, psis, trial_steps: int = 20) -> int:
+        """Time the candidate schedules on a scratch copy of ``psis`` and keep
+        the fastest; returns the chosen setting."""
+        scratch = self.pack(psis)
+        c = ctypes.c_int(0)
+        _check(self.lib.hfgpe_autotune(self.handle, self._ptr(scratch), int(trial_steps),
+                                       ctypes.byref(c)), "hfgpe_autotune")
+        return c.value
 
     def device_status(self) -> int:
         return int(self.lib.hfgpe_device_status(self.handle))

@@ -60,6 +60,7 @@ struct hfgpe_plan {
     double dt = 0.0;
     hfgpe_options opts{};
     hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;  // graph mode on the legacy default stream
     SchemeDev scheme{};
     std::vector<InstDev> insts;
     std::vector<int64_t> offsets;
@@ -78,6 +79,13 @@ struct hfgpe_plan {
     int nblk = 1;
     double2 *d_cistab = nullptr;  // exp(-i j pi/32), j < 64, hi then lo words
     double2 *d_twtab = nullptr;   // d-D: exp(-2 pi i q / 2^twlog)
+    // d-D graph replay: a block of kGraphSteps steps captured once per record
+    // row stride; the pass kernels add *d_graph_base to their step offsets
+    int *d_graph_base = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_rec_steps = -1;
+    int graph_grid = -1;
+    void *graph_psi = nullptr;
     int twlog = 0;
     double *d_vtab = nullptr;  // d-D: V_I factor per axis on its grid
     int vtab_stride = 0;
@@ -102,6 +110,9 @@ struct hfgpe_plan {
         if (d_vtab) (void)hipFree(d_vtab);
         if (d_cistab) (void)hipFree(d_cistab);
         if (d_twtab) (void)hipFree(d_twtab);
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (own_stream) (void)hipStreamDestroy(own_stream);
+        if (d_graph_base) (void)hipFree(d_graph_base);
         if (d_kpart) (void)hipFree(d_kpart);
         for (auto *v : {&ev_step, &ev_coeff, &ev_pool})
             for (auto &e : *v) {
@@ -254,6 +265,96 @@ static int take_events(hfgpe_plan *P, std::pair<hipEvent_t, hipEvent_t> &out)
     return HFGPE_OK;
 }
 
+constexpr int kGraphSteps = 16;
+
+// Enqueue the m x d axis passes of one step (record row `step`, or the
+// device-side base + step when base is given).  profile: bracket each pass
+// with events (not allowed while capturing).
+static int nd_step(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const int *base, bool first,
+                   bool profile)
+{
+    const int m = P->scheme.m;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < P->ndim; ++j) {
+            LaunchND L;
+            std::memset(&L, 0, sizeof(L));
+            L.insts = P->d_insts;
+            L.n_inst = P->n_inst;
+            L.rec = P->d_rec;
+            L.rec_open = P->d_rec_open;
+            L.vtab = P->d_vtab;
+            L.vtab_stride = P->vtab_stride;
+            L.cistab = P->d_cistab;
+            L.twtab = P->d_twtab;
+            L.twlog = P->twlog;
+            L.psi = d_psi;
+            L.c64 = P->dtype == HFGPE_C64;
+            L.ndim = P->ndim;
+            for (int a = 0; a < 3; ++a) L.n[a] = P->insts[0].n[a];
+            L.axis = j;
+            L.stage = i;
+            L.m = m;
+            L.rec_steps = rec_steps;
+            L.step = step;
+            L.step_base = base;
+            L.apply_open = (first && i == 0 && j == 0) ? 1 : 0;
+            L.apply_close = (j == P->ndim - 1) ? 1 : 0;
+            L.grid = P->nd_grid;
+            L.stream = P->stream;
+            std::pair<hipEvent_t, hipEvent_t> es{};
+            const bool ev = profile && P->opts.profile;
+            if (ev) {
+                int rc = take_events(P, es);
+                if (rc) return rc;
+                HIP_TRY(hipEventRecord(es.first, P->stream));
+            }
+            HIP_TRY(launch_nd_pass(L));
+            if (ev) {
+                HIP_TRY(hipEventRecord(es.second, P->stream));
+                P->ev_step.push_back(es);
+            }
+        }
+    return HFGPE_OK;
+}
+
+// Capture (once per record stride, workgroup count and buffer) the graph of
+// kGraphSteps steps followed by the base advance.
+static int nd_graph_ready(hfgpe_plan *P, void *d_psi, int rec_steps)
+{
+    if (P->graph_exec && P->graph_rec_steps == rec_steps && P->graph_grid == P->nd_grid && P->graph_psi == d_psi)
+        return HFGPE_OK;
+    if (P->graph_exec) {
+        (void)hipGraphExecDestroy(P->graph_exec);
+        P->graph_exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+    int rc = HFGPE_OK;
+    for (int s = 0; s < kGraphSteps && rc == HFGPE_OK; ++s) rc = nd_step(P, d_psi, rec_steps, s, P->d_graph_base, false, false);
+    hipError_t e = (rc == HFGPE_OK) ? launch_advance_base(P->d_graph_base, kGraphSteps, P->stream) : hipSuccess;
+    hipError_t ee = hipStreamEndCapture(P->stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess || ee != hipSuccess) {
+        g_last_hip_error = (int)(e != hipSuccess ? e : ee);
+        if (g) (void)hipGraphDestroy(g);
+        return HFGPE_E_HIP;
+    }
+    e = hipGraphInstantiate(&P->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        P->graph_exec = nullptr;
+        return HFGPE_E_HIP;
+    }
+    P->graph_rec_steps = rec_steps;
+    P->graph_grid = P->nd_grid;
+    P->graph_psi = d_psi;
+    return HFGPE_OK;
+}
+
 extern "C" {
 
 const char *hfgpe_status_string(int status)
@@ -364,6 +465,15 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
     P->dt = dt;
     if (opts) P->opts = *opts;
     P->stream = (hipStream_t)hip_stream;
+    if (P->opts.use_graph && P->stream == nullptr && n_inst > 0 && nd > 1) {
+        // the legacy default stream cannot be captured: use a blocking stream of
+        // our own, which the default stream orders against implicitly
+        if (hipStreamCreate(&P->own_stream) != hipSuccess) {
+            delete P;
+            return HFGPE_E_HIP;
+        }
+        P->stream = P->own_stream;
+    }
     P->scheme = S;
     P->insts.resize(n_inst);
     P->offsets.resize(n_inst + 1);
@@ -497,6 +607,11 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         }
         ALLOC_TRY(P->d_twtab, sizeof(double2) * tw.size());
         COPY_TRY(P->d_twtab, tw.data(), sizeof(double2) * tw.size());
+        ALLOC_TRY(P->d_graph_base, sizeof(int));
+        {
+            int z = 0;
+            COPY_TRY(P->d_graph_base, &z, sizeof(int));
+        }
     }
 #undef ALLOC_TRY
 #undef COPY_TRY
@@ -553,44 +668,22 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
             P->ev_coeff.push_back(ec);
         }
         if (P->ndim > 1) {
-            for (int st = 0; st < k; ++st)
-                for (int i = 0; i < m; ++i)
-                    for (int j = 0; j < P->ndim; ++j) {
-                        LaunchND L;
-                        L.insts = P->d_insts;
-                        L.n_inst = P->n_inst;
-                        L.rec = P->d_rec;
-                        L.rec_open = P->d_rec_open;
-                        L.vtab = P->d_vtab;
-                        L.vtab_stride = P->vtab_stride;
-                        L.cistab = P->d_cistab;
-                        L.twtab = P->d_twtab;
-                        L.twlog = P->twlog;
-                        L.psi = d_psi;
-                        L.c64 = P->dtype == HFGPE_C64;
-                        L.ndim = P->ndim;
-                        for (int a = 0; a < 3; ++a) L.n[a] = P->insts[0].n[a];
-                        L.axis = j;
-                        L.stage = i;
-                        L.m = m;
-                        L.rec_steps = k;
-                        L.step = st;
-                        L.apply_open = (s0 == 0 && st == 0 && i == 0 && j == 0) ? 1 : 0;
-                        L.apply_close = (j == P->ndim - 1) ? 1 : 0;
-                        L.grid = P->nd_grid;
-                        L.stream = P->stream;
-                        std::pair<hipEvent_t, hipEvent_t> es{};
-                        if (P->opts.profile) {
-                            int rc = take_events(P, es);
-                            if (rc) return rc;
-                            HIP_TRY(hipEventRecord(es.first, P->stream));
-                        }
-                        HIP_TRY(launch_nd_pass(L));
-                        if (P->opts.profile) {
-                            HIP_TRY(hipEventRecord(es.second, P->stream));
-                            P->ev_step.push_back(es);
-                        }
-                    }
+            int st = 0;
+            if (s0 == 0) {  // the opening x-phase rides on the first step's first pass
+                int rc = nd_step(P, d_psi, k, 0, nullptr, true, true);
+                if (rc) return rc;
+                st = 1;
+            }
+            if (P->opts.use_graph && k - st >= kGraphSteps) {
+                int rc = nd_graph_ready(P, d_psi, k);
+                if (rc) return rc;
+                HIP_TRY(launch_set_base(P->d_graph_base, st, P->stream));
+                for (; st + kGraphSteps <= k; st += kGraphSteps) HIP_TRY(hipGraphLaunch(P->graph_exec, P->stream));
+            }
+            for (; st < k; ++st) {
+                int rc = nd_step(P, d_psi, k, st, nullptr, false, true);
+                if (rc) return rc;
+            }
             continue;
         }
         for (int sb = 0; sb < k; sb += per_launch) {
@@ -772,6 +865,66 @@ int hfgpe_stage_coeffs_params(const hfgpe_params *params, int ndim, const hfgpe_
         }
     }
     return HFGPE_OK;
+}
+
+int hfgpe_autotune(hfgpe_plan *P, void *d_scratch, int64_t trial_steps, int *choice)
+{
+    if (!P || trial_steps < 1) return HFGPE_E_INVALID_ARG;
+    if (P->n_inst == 0) {
+        if (choice) *choice = 0;
+        return HFGPE_OK;
+    }
+    if (!d_scratch) return HFGPE_E_INVALID_ARG;
+    // candidate schedules
+    std::vector<int> cand;
+    int64_t groups = 0;
+    if (P->ndim > 1) {
+        int64_t pts = P->offsets[1];
+        for (int j = 0; j < P->ndim; ++j)
+            groups = std::max<int64_t>(groups, (int64_t)P->n_inst * ((pts / P->insts[0].n[j]) >> nd_group_log(P->insts[0].n, j)));
+        for (int g : {256, 512, 768, 1024, 1536, 2048})
+            if (g <= groups || cand.empty()) cand.push_back((int)std::min<int64_t>(g, groups));
+    } else {
+        // steps per resident launch: the whole chunk (0) or shorter launches
+        for (int64_t k : {(int64_t)0, (int64_t)1024, (int64_t)256})
+            if (k == 0 || k < trial_steps) cand.push_back((int)k);
+    }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int saved_profile = P->opts.profile;
+    P->opts.profile = 0;
+    float best = 0.0f;
+    int best_c = cand[0];
+    int rc = HFGPE_OK;
+    for (size_t ci = 0; ci < cand.size() && rc == HFGPE_OK; ++ci) {
+        if (P->ndim > 1) P->nd_grid = cand[ci];
+        else P->opts.steps_per_launch = cand[ci];
+        rc = hfgpe_evolve(P, d_scratch, 0.0, 1);  // warm up this configuration
+        if (rc) break;
+        if (hipEventRecord(e0, P->stream) != hipSuccess) { rc = HFGPE_E_HIP; break; }
+        rc = hfgpe_evolve(P, d_scratch, 0.0, trial_steps);
+        if (rc) break;
+        if (hipEventRecord(e1, P->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = HFGPE_E_HIP;
+            break;
+        }
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = HFGPE_E_HIP; break; }
+        if (ci == 0 || ms < best) {
+            best = ms;
+            best_c = cand[ci];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P->opts.profile = saved_profile;
+    if (P->ndim > 1) P->nd_grid = best_c;
+    else P->opts.steps_per_launch = best_c;
+    if (choice) *choice = best_c;
+    return rc;
 }
 
 int hfgpe_profile(hfgpe_plan *P, double *step_ms, double *coeff_ms, int64_t *step_launches)

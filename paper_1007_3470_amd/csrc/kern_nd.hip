@@ -39,8 +39,12 @@ __global__ __launch_bounds__(kThreadsND, 2) void hfnd_pass_kernel(
     const InstDev *__restrict__ insts, int n_inst, const Rec *__restrict__ rec,
     const Rec *__restrict__ rec_open, const double *__restrict__ vtab, int vtab_stride,
     const double2 *__restrict__ cistab, const double2 *__restrict__ twtab, int twlog,
-    Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step)
+    Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step_off,
+    const int *__restrict__ step_base)
 {
+    // step within the coefficient records: a fixed offset, plus a device-side
+    // base when the launch is replayed from a captured graph
+    const int step = step_off + (step_base ? *step_base : 0);
     constexpr int LOGP = Log2<P>::value;
     constexpr int LDS_ELEMS = kThreadsND * P + ((kThreadsND * P) >> kPadShift);
     __shared__ double2 lds[LDS_ELEMS];
@@ -268,7 +272,7 @@ static hipError_t launch_pass_mode(const LaunchND &L)
     int threads = 1 << (lG + sh.logn[L.axis] - Log2<P>::value);
     hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE>), dim3(L.grid), dim3(threads), 0, L.stream, L.insts,
                        L.n_inst, L.rec, L.rec_open, L.vtab, L.vtab_stride, L.cistab, L.twtab, L.twlog,
-                       (Store *)L.psi, sh, L.axis, lG, L.stage, L.m, L.rec_steps, L.step);
+                       (Store *)L.psi, sh, L.axis, lG, L.stage, L.m, L.rec_steps, L.step, L.step_base);
     return hipGetLastError();
 }
 
@@ -325,6 +329,21 @@ hipError_t launch_kinetic_nd(const LaunchND &L, int nblk, double *part)
 {
     if (L.n_inst <= 0) return hipSuccess;
     return L.c64 ? launch_kin_store<float2>(L, nblk, part) : launch_kin_store<double2>(L, nblk, part);
+}
+
+__global__ void advance_base_kernel(int *base, int by) { *base += by; }
+__global__ void set_base_kernel(int *base, int v) { *base = v; }
+
+hipError_t launch_set_base(int *base, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_base_kernel, dim3(1), dim3(1), 0, s, base, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_base(int *base, int by, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_base_kernel, dim3(1), dim3(1), 0, s, base, by);
+    return hipGetLastError();
 }
 
 int points_per_thread_nd(int n)

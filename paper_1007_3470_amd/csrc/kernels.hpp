@@ -93,6 +93,7 @@ struct LaunchND {
     int ndim;
     int n[3];
     int axis, stage, m, rec_steps, step;
+    const int *step_base;  // device int added to step (graph replay), or null
     int apply_open, apply_close;
     int grid;  // persistent workgroups
     hipStream_t stream;
@@ -102,5 +103,8 @@ hipError_t launch_nd_pass(const LaunchND &L);
 hipError_t launch_kinetic_nd(const LaunchND &L, int nblk, double *part);
 int points_per_thread_nd(int n);
 int nd_group_log(const int *n, int axis);
+// one-thread kernels that set / advance the device-side step base of a graph
+hipError_t launch_set_base(int *base, int v, hipStream_t s);
+hipError_t launch_advance_base(int *base, int by, hipStream_t s);
 
 }  // namespace hfgpe
