@@ -77,6 +77,39 @@ def timed_evolve(pkg, torch, w, dtype, K, warmup, **kw):
     return plan, buf, wall, gpu_ms, step_ms, coeff_ms, launches
 
 
+def nd_workload(pkg, torch, W, w, sc_bytes):
+    """Secondary measurement: a d-D workload at full size, c64 and c128, graph
+    replay; per-pass HBM roofline from the library's HIP events."""
+    out = {}
+    res = {}
+    for dtype, sc in (("c64", 8), ("c128", 16)):
+        plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, use_graph=True)
+        scratch = plan.pack(w.psi0)
+        plan.evolve(scratch, 0.0, 2)
+        del scratch
+        buf = plan.pack(w.psi0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.evolve(buf, 0.0, w.nsteps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[dtype] = plan.unpack(buf)
+        # per-pass time from a short profiled run without graphs
+        prof = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, profile=True)
+        b2 = prof.pack(w.psi0)
+        prof.evolve(b2, 0.0, 2)
+        prof.profile()
+        prof.evolve(b2, 0.0, 8)
+        kms, _, nl = prof.profile()
+        pass_s = kms / 1e3 / nl
+        bw = 2.0 * sc * w.points / pass_s / 1e9
+        out[dtype] = {"value": w.points * w.nsteps / wall, "ms_per_step": wall * 1e3 / w.nsteps,
+                      "pass_us": pass_s * 1e6, "pass_GBs": bw, "pass_frac_of_hbm_peak": bw / HBM_PEAK_GBS}
+    out["l2_c64_vs_c128_max"] = max(W.rel_l2(a, b) for a, b in zip(res["c64"], res["c128"]))
+    out["workload"] = w.notes + ", %s + %s, dt=%g, %d steps" % (w.scheme, w.ho_rule, w.dt, w.nsteps)
+    return out
+
+
 def load_traffic(src_hash):
     try:
         with open(TRAFFIC_FILE) as f:
@@ -118,6 +151,7 @@ def main(argv=None):
     ap.add_argument("--cpu-per-size", type=int, default=8,
                     help="oracle sample: instances per grid size (0 disables)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-nd", action="store_true", help="skip the 2-D and 3-D workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -188,6 +222,9 @@ def main(argv=None):
         "roofline": roof,
         "wall_s": {"c64": wall64, "c128": wall128},
     }
+    if not args.no_nd:
+        line["other_workloads"] = {"gpe_2d": nd_workload(pkg, torch, W, W.gpe_2d(), 8),
+                                   "gpe_3d": nd_workload(pkg, torch, W, W.gpe_3d(), 8)}
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

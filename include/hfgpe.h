@@ -68,7 +68,10 @@ typedef enum { HFGPE_C64 = 0, HFGPE_C128 = 1 } hfgpe_dtype;
 typedef enum {
     HFGPE_HO_EXACT_CONST = 0, /* Lemma 2; omega must be constant in time        */
     HFGPE_HO_CF4 = 1,         /* Eq. CommutatorFree + Theorem 2 (order 4)       */
-    HFGPE_HO_MAGNUS6 = 2      /* sixth-order Magnus of Sec. 4.2 + Theorem 1     */
+    HFGPE_HO_MAGNUS6 = 2,     /* sixth-order Magnus of Sec. 4.2 + Theorem 1     */
+    HFGPE_FSPLIT = 3          /* the Fourier split (i) of Sec. 2.1, the paper's
+                                 comparison method: A = p^2/(2 mu) as an exact
+                                 drift, the harmonic potential moved into B */
 } hfgpe_ho_rule;
 
 /* Uniform periodic grid of one instance. */

@@ -39,7 +39,7 @@ _SO = os.path.join(_HERE, "libhfgpe_oracle.so")
 _LIB = None
 
 NPAR = 36
-HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2}
+HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2, "fsplit": 3}
 _ERRORS = {-1: "invalid argument", -2: "singular stage (g = 0)",
            -3: "non-positive squared frequency", -4: "out of memory"}
 

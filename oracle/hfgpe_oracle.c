@@ -20,6 +20,8 @@
  *     Magnus generator of Sec. 4.2) and then factored as
  *     S = K(f) D(g) K(e), i.e. g = S12, e = (1-S11)/g, f = (1-S22)/g, which is
  *     the content of Lemma 2 and Theorems 1-2 (Sec. 2.2);
+ *   - the Fourier split (i) of Sec. 2.1 as the comparison method: exact
+ *     drift D(a_i h/mu) and a B flow that carries the harmonic potential;
  *   - one time step as Table "algorithm" of Sec. 2 with the HO split (ii):
  *     the B flow (Lemma 1, frozen time) and the A flow = K(f) D(g) K(e),
  *     applied one after the other WITHOUT merging adjacent x-phases (the
@@ -53,7 +55,7 @@
 #define ORC_PI 3.14159265358979323846
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ESINGULAR = -2, ORC_EFREQ = -3, ORC_ENOMEM = -4 };
-enum { ORC_HO_EXACT_CONST = 0, ORC_HO_CF4 = 1, ORC_HO_MAGNUS6 = 2 };
+enum { ORC_HO_EXACT_CONST = 0, ORC_HO_CF4 = 1, ORC_HO_MAGNUS6 = 2, ORC_FSPLIT = 3 };
 
 /* ------------------------------------------------------------------------ */
 /* Parameter access                                                          */
@@ -340,6 +342,7 @@ int orc_stage_matrix(int rule, const double *par, int axis, double t0, double ta
 int orc_stage_coeffs(int ndim, const double *par, int m, const double *a, int rule,
                      double dt, double tn, double *out)
 {
+    if (rule == ORC_FSPLIT) return ORC_EINVAL;
     double tau = tn;
     for (int i = 0; i < m; ++i) {
         for (int j = 0; j < ndim; ++j) {
@@ -484,12 +487,52 @@ static int apply_D(const grid_t *G, double *u, const double *g)
     return orc_fftn(G->ndim, G->n, u, +1);
 }
 
+/* B flow of the Fourier split (Eq. FourierSplit) frozen at tau: the harmonic
+ * potential joins the pointwise phase,
+ * u <- exp(-i dt w (sum_j mu omega_j(tau)^2 x_j^2/2 + eps V_I + sigma |u|^2)) u. */
+static void apply_B_fsplit(const grid_t *G, double *u, double dt, double w, double tau)
+{
+    if (w == 0.0) return;
+    double sig = par_sigma(G->par, tau), mu = par_mu(G->par);
+    double q[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < G->ndim; ++j) {
+        double om = par_omega(G->par, j, tau);
+        q[j] = mu * om * om;
+    }
+    for (long idx = 0; idx < G->total; ++idx) {
+        double harm = 0.0;
+        for (int j = 0; j < G->ndim; ++j)
+            harm += q[j] * axis_table(G, G->x2h, j)[axis_index(G, idx, j)];
+        double a2 = u[2 * idx] * u[2 * idx] + u[2 * idx + 1] * u[2 * idx + 1];
+        mul_phase(u + 2 * idx, dt * w * (harm + G->vi[idx] + sig * a2));
+    }
+}
+
+/* One step of the Fourier split: A = p^2/(2 mu) is the exact drift D(a_i dt / mu),
+ * B carries the harmonic potential (Eq. FourierSplit with Table "algorithm"). */
+static int step_fsplit(const grid_t *G, double *u, int m, const double *a, const double *b, double dt,
+                       double tn)
+{
+    double tau = tn;
+    apply_B_fsplit(G, u, dt, b[0], tau);
+    for (int i = 0; i < m; ++i) {
+        double g[3];
+        for (int j = 0; j < G->ndim; ++j) g[j] = a[i] * dt / par_mu(G->par);
+        int rc = apply_D(G, u, g);
+        if (rc) return rc;
+        tau = tau + a[i] * dt;
+        apply_B_fsplit(G, u, dt, b[i + 1], tau);
+    }
+    return ORC_OK;
+}
+
 /* One step t_n -> t_n + dt of the composition (Eq. prod-gen, Table
  * "algorithm"), with each A flow replaced by its K(f) D(g) K(e) factorisation.
  * b holds m+1 weights (BAB form; b[0] = 0 gives an ABA-type scheme). */
 static int step_once(const grid_t *G, double *u, int m, const double *a, const double *b,
                      int rule, double dt, double tn)
 {
+    if (rule == ORC_FSPLIT) return step_fsplit(G, u, m, a, b, dt, tn);
     double tau = tn;
     apply_B(G, u, dt, b[0], tau);
     for (int i = 0; i < m; ++i) {

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhfgpe.so")
 
 HFGPE_C64, HFGPE_C128 = 0, 1
-HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2}
+HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2, "fsplit": 3}
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "singular stage",
           -4: "non-positive frequency", -5: "allocation failed", -6: "HIP error",
           -7: "non-finite coefficient", -8: "no gfx950 device"}

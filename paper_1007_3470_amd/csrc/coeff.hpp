@@ -104,12 +104,21 @@ __host__ __device__ inline Fge fge_magnus6(double mu, const SinMod &om, double t
     return r;
 }
 
+// Fourier split (Eq. FourierSplit): the A flow is the free drift over tau, no
+// chirps; the harmonic potential is carried by the B phase (see kern_coeff).
+__host__ __device__ inline Fge fge_fsplit(double mu, double tau)
+{
+    Fge r{0.0, tau / mu, 0.0, 0};
+    return r;
+}
+
 __host__ __device__ inline Fge fge_stage(int rule, double mu, const SinMod &om, double t0, double tau)
 {
     switch (rule) {
     case 0: return fge_exact(mu, om.v0, tau);
     case 1: return fge_cf4(mu, om, t0, tau);
     case 2: return fge_magnus6(mu, om, t0, tau);
+    case 3: return fge_fsplit(mu, tau);
     default: { Fge r{0.0, 0.0, 0.0, -1}; return r; }
     }
 }

@@ -145,6 +145,7 @@ int validate_instance(const hfgpe_params &p, int nd, const SchemeDev &S, double 
             !std::isfinite(v.k) || !std::isfinite(v.phi))
             return HFGPE_E_INVALID_ARG;
     }
+    if (S.rule == HFGPE_FSPLIT) return HFGPE_OK;  // free drift: no singular steps
     double amax = 0.0;
     for (int i = 0; i < S.m; ++i) amax = std::max(amax, std::fabs(S.a[i]));
     for (int j = 0; j < nd; ++j) {
@@ -180,7 +181,7 @@ int validate_instance(const hfgpe_params &p, int nd, const SchemeDev &S, double 
 int build_scheme(const hfgpe_scheme *s, int nd, SchemeDev &S)
 {
     if (!s || !s->a || !s->b || s->m < 1 || s->m > kMaxStages) return HFGPE_E_INVALID_ARG;
-    if (s->ho_rule < HFGPE_HO_EXACT_CONST || s->ho_rule > HFGPE_HO_MAGNUS6) return HFGPE_E_INVALID_ARG;
+    if (s->ho_rule < HFGPE_HO_EXACT_CONST || s->ho_rule > HFGPE_FSPLIT) return HFGPE_E_INVALID_ARG;
     std::memset(&S, 0, sizeof(S));
     S.m = s->m;
     S.rule = (int)s->ho_rule;

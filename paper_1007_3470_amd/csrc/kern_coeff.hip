@@ -10,7 +10,8 @@
 //   inside a step:         chi = f_i + e_{i+1},      w = dt b_{i+1} at tau_{i+1}
 //   across a step boundary: chi = f_{m-1} + e'_0,     w = dt (b_m + b_0) at t_{n+1}
 //   after the last step:    chi = f_{m-1},            w = dt b_m at t_{n+1}
-// and s = w sigma(tau).  The opening phase of an evolve call
+// and s = w sigma(tau).  Under the Fourier split (no chirps) chi is instead
+// w mu omega_j(tau)^2, the harmonic potential of the B flow.  The opening phase of an evolve call
 // (chi = e_0(t_0), w = dt b_0 at t_0) goes to rec_open.
 #include <hip/hip_runtime.h>
 
@@ -56,6 +57,11 @@ __global__ void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
         }
         o.w = dt * sch->b[0];
         o.s = o.w * sinmod(I.sig, tn);
+        if (rule == 3)
+            for (int j = 0; j < nd; ++j) {
+                const double om = sinmod(I.om[j], tn);
+                o.chi[j] += o.w * I.mu * om * om;
+            }
         rec_open[inst] = o;
     }
     for (int i = 0; i < m; ++i) {
@@ -88,6 +94,11 @@ __global__ void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
             r.w = dt * sch->b[m];
         }
         r.s = r.w * sinmod(I.sig, tau_next);
+        if (rule == 3)  // Fourier split: the harmonic potential is part of B
+            for (int j = 0; j < nd; ++j) {
+                const double om = sinmod(I.om[j], tau_next);
+                r.chi[j] += r.w * I.mu * om * om;
+            }
         bool finite = isfinite(r.w) && isfinite(r.s);
         for (int j = 0; j < 3; ++j) finite = finite && isfinite(r.g[j]) && isfinite(r.chi[j]);
         if (!finite) raise_err(err, -7);

@@ -219,3 +219,14 @@ def test_batch_1d_full_size_sampled(pkg, dtype):
     drift = np.abs(nrm - n0).max()
     say("batch_1d full %s max norm drift %.3e" % (dtype, drift))
     assert drift < (1e-11 if dtype == "c128" else 1e-4)
+
+
+@pytest.mark.parametrize("scheme", ["leapfrog", "ni4_82", "srkn6_4"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fourier_split_1d(pkg, scheme, dtype):
+    w = W.batch_1d(n_inst=5, sizes=(256, 1024, 2048), nsteps=40, seed=17, scheme=scheme, rule="fsplit")
+    _, _, got = run_gpu(pkg, w, dtype)
+    for k in range(len(w.instances)):
+        err = W.rel_l2(got[k], oracle_run(w, k))
+        say("fsplit %s %s k=%d rel_l2 %.3e" % (scheme, dtype, k, err))
+        assert err < TOL[dtype]

@@ -198,3 +198,15 @@ def test_autotune_keeps_results(pkg):
     got = plan.unpack(buf)
     for k in range(4):
         assert np.array_equal(got[k], ref[k])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fourier_split_nd(pkg, dtype):
+    for w in (W.gpe_2d(n=64, n_inst=2, nsteps=15, rule="fsplit"),
+              W.gpe_3d(n=32, nsteps=4, rule="fsplit")):
+        _, _, got = run_gpu(pkg, w, dtype)
+        for k, inst in enumerate(w.instances):
+            ref = oracle.evolve(inst, w.psi0[k], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
+            err = W.rel_l2(got[k], ref)
+            say("fsplit %dD %s k=%d rel_l2 %.3e" % (inst.ndim, dtype, k, err))
+            assert err < TOL[dtype]

@@ -417,3 +417,49 @@ def test_norm_and_energy_closed_forms():
     assert pot == pytest.approx((0.5 + eps) * (x0 ** 2 + 0.5), abs=1e-13)
     assert inter == pytest.approx(sig / (2 * math.sqrt(2 * math.pi)), abs=1e-13)
     assert E == pytest.approx(kin + pot + inter, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# The Fourier split (Eq. FourierSplit), the paper's comparison method
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,order", [("leapfrog", 2), ("ni5_84", 4), ("srkn6_4", 4)])
+def test_fsplit_order_time_dependent_linear(scheme, order):
+    inst = linear_inst(n=256, lo=-12.0, hi=12.0, omega=(1.2, 0.3, 2.0, 0.0), mu=1.3)
+    x0 = 0.7
+    x = inst.axis(0)
+    s = inst.mu * 1.2
+    psi0 = np.exp(-s * (x - x0) ** 2 / 2)
+    T = 1.2
+    ref = gaussian_packet(inst, -s / 2, s * x0, -s * x0 * x0 / 2, 0.0, T)
+    ref = ref * (np.linalg.norm(psi0) / np.linalg.norm(ref))  # same constant factor
+    errs = []
+    for nst in (12, 24, 48):
+        u = oracle.evolve(inst, psi0, scheme, "fsplit", T / nst, 0.0, nst)
+        errs.append(W.rel_l2(u, ref))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > order - 0.4, (errs, rates)
+
+
+def _f_vs_hf(sigma, lo, hi, n=256, T=2.0, h=0.05):
+    inst = W.Instance(1, (n, 1, 1), (lo, 0, 0), (hi, 1, 1), sigma=(sigma, 0, 0, 0))
+    x = inst.axis(0)
+    psi0 = np.exp(-(x - 1.0) ** 2 / 2).astype(complex)
+    psi0 /= math.sqrt(inst.cell * np.sum(abs(psi0) ** 2))
+    ref = oracle.evolve(inst, psi0, "ni5_84", "exact_const", h / 16, 0.0, int(round(T / h)) * 16)
+    nst = int(round(T / h))
+    e_hf = W.rel_l2(oracle.evolve(inst, psi0, "leapfrog", "exact_const", h, 0.0, nst), ref)
+    e_f = W.rel_l2(oracle.evolve(inst, psi0, "leapfrog", "fsplit", h, 0.0, nst), ref)
+    return e_hf, e_f
+
+
+def test_hf_beats_fsplit_for_weak_perturbation():
+    # Sec. 4.1: with sigma = 0.01 the HO split is far more accurate at the same
+    # number of FFT pairs
+    e_hf, e_f = _f_vs_hf(0.01, -20.0, 20.0)
+    assert e_hf * 100 < e_f, (e_hf, e_f)
+
+
+def test_hf_matches_fsplit_for_strong_nonlinearity():
+    # Sec. 4.1: for sigma = 100 the two splits reach similar precision
+    e_hf, e_f = _f_vs_hf(100.0, -30.0, 30.0, n=512, h=0.01, T=0.5)
+    assert 0.1 < e_hf / e_f < 10.0, (e_hf, e_f)
