@@ -152,6 +152,10 @@ def main(argv=None):
                     help="oracle sample: instances per grid size (0 disables)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-nd", action="store_true", help="skip the 2-D and 3-D workloads")
+    ap.add_argument("--nd-steps", type=int, default=0,
+                    help="steps of the 2-D and 3-D workloads (0 = their full runs)")
+    ap.add_argument("--nd-only", action="store_true",
+                    help="only the 2-D and 3-D workloads (for profiling their kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args(argv)
@@ -169,6 +173,12 @@ def main(argv=None):
     torch.cuda.set_device(0)
     pkg.load()
     K, WU = args.steps, args.warmup
+    nd_kw = {"nsteps": args.nd_steps} if args.nd_steps > 0 else {}
+    if args.nd_only:
+        print(json.dumps({"other_workloads": {"gpe_2d": nd_workload(pkg, torch, W, W.gpe_2d(**nd_kw), 8),
+                                              "gpe_3d": nd_workload(pkg, torch, W, W.gpe_3d(**nd_kw), 8)}}),
+              flush=True)
+        return 0
     w = W.batch_1d(nsteps=K)
     npts = w.points
     m = len(pkg.scheme_preset(w.scheme)[0])
@@ -223,8 +233,8 @@ def main(argv=None):
         "wall_s": {"c64": wall64, "c128": wall128},
     }
     if not args.no_nd:
-        line["other_workloads"] = {"gpe_2d": nd_workload(pkg, torch, W, W.gpe_2d(), 8),
-                                   "gpe_3d": nd_workload(pkg, torch, W, W.gpe_3d(), 8)}
+        line["other_workloads"] = {"gpe_2d": nd_workload(pkg, torch, W, W.gpe_2d(**nd_kw), 8),
+                                   "gpe_3d": nd_workload(pkg, torch, W, W.gpe_3d(**nd_kw), 8)}
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
