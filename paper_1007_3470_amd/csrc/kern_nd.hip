@@ -294,7 +294,9 @@ static hipError_t launch_pass_store(const LaunchND &L)
     case 1: return launch_pass_p<Store, 1, 1>(L);
     case 2: return launch_pass_p<Store, 2, 1>(L);
     case 4: return launch_pass_p<Store, 4, 1>(L);
-    case 8: return launch_pass_p<Store, 8, 4>(L);
+    // axes up to 512 points need at most 3 radix passes: the smaller register
+    // file of the MAXS = 3 instance leaves the drift-only passes spill-free
+    case 8: return L.n[L.axis] <= 512 ? launch_pass_p<Store, 8, 3>(L) : launch_pass_p<Store, 8, 4>(L);
     default: return hipErrorInvalidValue;
     }
 }
