@@ -590,7 +590,7 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         // persistent workgroups for the axis passes: enough to fill the chip
         int64_t groups = 0;
         for (int j = 0; j < nd; ++j) {
-            int lG = nd_group_log(P->insts[0].n, j);
+            int lG = nd_group_log(P->insts[0].n, j, nd_threads(P->insts[0].n, j, dtype == HFGPE_C64));
             groups = std::max<int64_t>(groups, (int64_t)n_inst * ((pts / P->insts[0].n[j]) >> lG));
         }
         // persistent workgroups: a few per CU, each looping over many pencil groups
@@ -882,7 +882,8 @@ int hfgpe_autotune(hfgpe_plan *P, void *d_scratch, int64_t trial_steps, int *cho
     if (P->ndim > 1) {
         int64_t pts = P->offsets[1];
         for (int j = 0; j < P->ndim; ++j)
-            groups = std::max<int64_t>(groups, (int64_t)P->n_inst * ((pts / P->insts[0].n[j]) >> nd_group_log(P->insts[0].n, j)));
+            groups = std::max<int64_t>(groups, (int64_t)P->n_inst * ((pts / P->insts[0].n[j]) >>
+                                                                    nd_group_log(P->insts[0].n, j, 256)));
         for (int g : {256, 512, 768, 1024, 1536, 2048})
             if (g <= groups || cand.empty()) cand.push_back((int)std::min<int64_t>(g, groups));
     } else {

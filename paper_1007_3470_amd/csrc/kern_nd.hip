@@ -24,6 +24,7 @@
 namespace hfgpe {
 
 constexpr int kThreadsND = 256;
+constexpr int kMaxAxisND = 1024;  // longest axis of a d-D plan
 
 struct NdShape {
     int ndim;
@@ -34,8 +35,8 @@ struct NdShape {
 // MODE: 0 = drift only, 1 = closing x-phase after the drift, 2 = opening
 // x-phase before it (separate instantiations keep unused phase code out of
 // the register allocation).
-template <typename Store, int P, int MAXS, int MODE>
-__global__ __launch_bounds__(kThreadsND, 2) void hfnd_pass_kernel(
+template <typename Store, int P, int MAXS, int MODE, int TPB>
+__global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     const InstDev *__restrict__ insts, int n_inst, const Rec *__restrict__ rec,
     const Rec *__restrict__ rec_open, const double *__restrict__ vtab, int vtab_stride,
     const double2 *__restrict__ cistab, const double2 *__restrict__ twtab, int twlog,
@@ -46,10 +47,10 @@ __global__ __launch_bounds__(kThreadsND, 2) void hfnd_pass_kernel(
     // base when the launch is replayed from a captured graph
     const int step = step_off + (step_base ? *step_base : 0);
     constexpr int LOGP = Log2<P>::value;
-    constexpr int LDS_ELEMS = kThreadsND * P + ((kThreadsND * P) >> kPadShift);
+    constexpr int LDS_ELEMS = TPB * P + ((TPB * P) >> kPadShift);
     __shared__ double2 lds[LDS_ELEMS];
     __shared__ double2 ctab[2 * kCisTable];
-    __shared__ double2 kfl[kThreadsND * P];  // drift factor of every wavenumber of the axis
+    __shared__ double2 kfl[kMaxAxisND];  // drift factor of every wavenumber of the axis
     load_cis_table(ctab, cistab);
     __syncthreads();
 
@@ -240,9 +241,9 @@ static NdShape make_shape(const LaunchND &L)
     return sh;
 }
 
-// log2 of the pencils per group of an axis pass: 256/T pencils, limited by the
+// log2 of the pencils per group of an axis pass: tpb/T pencils, limited by the
 // pencils available (x) or by the contiguous run of x positions (strided axes).
-int nd_group_log(const int *n, int axis)
+int nd_group_log(const int *n, int axis, int tpb)
 {
     int logn[3], ltot = 0, lstride = 0;
     for (int j = 0; j < 3; ++j) {
@@ -255,7 +256,9 @@ int nd_group_log(const int *n, int axis)
     int lp = 0;
     while ((1 << lp) < P) ++lp;
     int logT = logn[axis] - lp;
-    int lG = 8 - logT;
+    int ltpb = 0;
+    while ((1 << ltpb) < tpb) ++ltpb;
+    int lG = ltpb - logT;
     if (axis == 0) {
         if (lG > ltot - logn[axis]) lG = ltot - logn[axis];
     } else if (lG > lstride) {
@@ -264,16 +267,37 @@ int nd_group_log(const int *n, int axis)
     return lG;
 }
 
-template <typename Store, int P, int MAXS, int MODE>
-static hipError_t launch_pass_mode(const LaunchND &L)
+// Threads per workgroup of an axis pass.  A c64 strided axis whose 256-thread
+// group holds fewer than 8 pencils moves rows of under 64 bytes per access;
+// there a 512-thread group doubles the row length.  At 64 bytes and above the
+// two co-resident 256-thread groups (one loading while the other computes) are
+// faster than one 512-thread group with 128-byte rows.
+int nd_threads(const int *n, int axis, int c64)
+{
+    if (axis == 0 || !c64 || points_per_thread_nd(n[axis]) != 8) return kThreadsND;
+    const int lg256 = nd_group_log(n, axis, kThreadsND);
+    return (lg256 < 3 && nd_group_log(n, axis, 512) > lg256) ? 512 : kThreadsND;
+}
+
+template <typename Store, int P, int MAXS, int MODE, int TPB>
+static hipError_t launch_pass_tpb(const LaunchND &L)
 {
     NdShape sh = make_shape(L);
-    int lG = nd_group_log(L.n, L.axis);
+    int lG = nd_group_log(L.n, L.axis, TPB);
     int threads = 1 << (lG + sh.logn[L.axis] - Log2<P>::value);
-    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE>), dim3(L.grid), dim3(threads), 0, L.stream, L.insts,
+    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE, TPB>), dim3(L.grid), dim3(threads), 0, L.stream, L.insts,
                        L.n_inst, L.rec, L.rec_open, L.vtab, L.vtab_stride, L.cistab, L.twtab, L.twlog,
                        (Store *)L.psi, sh, L.axis, lG, L.stage, L.m, L.rec_steps, L.step, L.step_base);
     return hipGetLastError();
+}
+
+template <typename Store, int P, int MAXS, int MODE>
+static hipError_t launch_pass_mode(const LaunchND &L)
+{
+    if constexpr (P == 8 && sizeof(Store) == 8) {
+        if (nd_threads(L.n, L.axis, 1) == 512) return launch_pass_tpb<Store, P, MAXS, MODE, 512>(L);
+    }
+    return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND>(L);
 }
 
 template <typename Store, int P, int MAXS>

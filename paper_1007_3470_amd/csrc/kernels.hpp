@@ -102,7 +102,8 @@ hipError_t launch_nd_pass(const LaunchND &L);
 // Kinetic energy partials along L.axis: part[inst * nblk + b].
 hipError_t launch_kinetic_nd(const LaunchND &L, int nblk, double *part);
 int points_per_thread_nd(int n);
-int nd_group_log(const int *n, int axis);
+int nd_group_log(const int *n, int axis, int tpb);
+int nd_threads(const int *n, int axis, int c64);
 // one-thread kernels that set / advance the device-side step base of a graph
 hipError_t launch_set_base(int *base, int v, hipStream_t s);
 hipError_t launch_advance_base(int *base, int by, hipStream_t s);
