@@ -69,10 +69,20 @@ typedef enum {
     HFGPE_HO_EXACT_CONST = 0, /* Lemma 2; omega must be constant in time        */
     HFGPE_HO_CF4 = 1,         /* Eq. CommutatorFree + Theorem 2 (order 4)       */
     HFGPE_HO_MAGNUS6 = 2,     /* sixth-order Magnus of Sec. 4.2 + Theorem 1     */
-    HFGPE_FSPLIT = 3          /* the Fourier split (i) of Sec. 2.1, the paper's
+    HFGPE_FSPLIT = 3,         /* the Fourier split (i) of Sec. 2.1, the paper's
                                  comparison method: A = p^2/(2 mu) as an exact
                                  drift, the harmonic potential moved into B */
+    HFGPE_HO_FUNDAMENTAL = 4  /* the stage's 2x2 classical fundamental matrix
+                                 (Eq. HO(t)sol: the HO flow for any omega(t) is
+                                 one exponential of E, F, G) integrated
+                                 numerically as a product of ho_substeps
+                                 sixth-order Magnus sub-steps of Sec. 4.2, then
+                                 factored as K(f) D(g) K(e) (Theorem 1's
+                                 decomposition applied to the product) */
 } hfgpe_ho_rule;
+
+/* Largest number of sub-steps of the HFGPE_HO_FUNDAMENTAL rule. */
+#define HFGPE_MAX_HO_SUBSTEPS 256
 
 /* Uniform periodic grid of one instance. */
 typedef struct {
@@ -82,10 +92,23 @@ typedef struct {
     double hi[3];
 } hfgpe_grid;
 
-/* A positive quantity modulated in time: v(t) = v0 (1 + amp sin(freq t + phase)). */
+/* Time dependence of omega_j(t) and sigma(t). */
+typedef enum {
+    HFGPE_TF_SIN = 0,    /* v(t)   = v0 (1 + amp sin(freq t + phase))                  */
+    HFGPE_TF_SQ_SIN = 1, /* v(t)^2 = v0 (1 + amp sin(freq t + phase)); frequencies only:
+                            the modulated squared trap frequency of Sec. 4.2's first
+                            example (phase = pi/2 gives the cosine there)            */
+    HFGPE_TF_PULSE = 2   /* v(t)   = v0 (1 + amp t / cosh^2(freq (t - phase))): the
+                            short pulse of Sec. 4.2's second example (phase is the
+                            pulse centre; freq must be non-zero when amp is)          */
+} hfgpe_tf_kind;
+
+/* A time-dependent coefficient; zero-initialised kind is HFGPE_TF_SIN, and
+ * amp = 0 makes any kind constant (v0, or sqrt(v0) for HFGPE_TF_SQ_SIN). */
 typedef struct {
     double v0, amp, freq, phase;
-} hfgpe_sinmod;
+    int kind; /* hfgpe_tf_kind */
+} hfgpe_tfunc;
 
 /* One separable factor of the perturbation V_I:
  *   v(x) = (c0 + c2 x^2 + c4 x^4) * exp(-x^2 / gs) * cos(k x + phi),
@@ -97,9 +120,10 @@ typedef struct {
 /* Physical parameters of one instance. */
 typedef struct {
     double mu;              /* mass, > 0 */
-    hfgpe_sinmod omega[3];  /* trap frequency per axis (Eq. GP1b)  */
-    hfgpe_sinmod sigma;     /* mean-field coupling sigma(t) (Sec. 1); v0 may be
-                               negative (attractive) or zero (linear problem) */
+    hfgpe_tfunc omega[3];   /* trap frequency per axis (Eq. GP1b); must stay > 0 */
+    hfgpe_tfunc sigma;      /* mean-field coupling sigma(t) (Sec. 1); v0 may be
+                               negative (attractive) or zero (linear problem);
+                               kind HFGPE_TF_SIN or HFGPE_TF_PULSE */
     double eps;             /* strength of V_I */
     hfgpe_vfactor v[3];     /* V_I factors; set c0 = 1, rest 0, for "no factor" */
 } hfgpe_params;
@@ -111,6 +135,8 @@ typedef struct {
     const double *a;       /* m stage fractions, sum 1 */
     const double *b;       /* m+1 B weights, sum 1 */
     hfgpe_ho_rule ho_rule;
+    int ho_substeps;       /* HFGPE_HO_FUNDAMENTAL: Magnus sub-steps per stage,
+                              1..HFGPE_MAX_HO_SUBSTEPS (0 = 16); ignored otherwise */
 } hfgpe_scheme;
 
 /* Optional execution settings (zero-initialise for defaults). */

@@ -14,7 +14,10 @@ oscillator in linear and nonlinear Schroedinger equations", arXiv:1007.3470.
 Parity status per function (the pins live in ``tests/test_oracle_*.py``):
   fftn            pinned: brute-force DFT, round trip, Parseval
   stage_matrix    pinned: Lemma 2 / Theorem 1 / Theorem 2 closed forms,
-                  local order against an RK4-integrated fundamental matrix
+                  local order against an RK4-integrated fundamental matrix;
+                  the fundamental-matrix rule against scipy's DOP853 solution
+                  of the same 2x2 system, its sub-step order, and its
+                  reductions (one sub-step = Magnus6; constant omega = exact)
   stage_coeffs    pinned: K(f) D(g) K(e) product reproduces the stage matrix
   evolve          pinned: coherent-state closed form (linear, constant omega),
                   ground-state single step (Fig. 1 experiment), norm
@@ -38,8 +41,9 @@ _SRC = os.path.join(_HERE, "hfgpe_oracle.c")
 _SO = os.path.join(_HERE, "libhfgpe_oracle.so")
 _LIB = None
 
-NPAR = 36
-HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2, "fsplit": 3}
+NPAR = 40
+HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2, "fsplit": 3, "fundamental": 4}
+FUNDAMENTAL_DEFAULT_SUBSTEPS = 16
 _ERRORS = {-1: "invalid argument", -2: "singular stage (g = 0)",
            -3: "non-positive squared frequency", -4: "out of memory"}
 
@@ -62,12 +66,12 @@ def _lib():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         lib.orc_fftn.argtypes = [ctypes.c_int, ip, dp, ctypes.c_int]
-        lib.orc_stage_matrix.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double,
-                                         ctypes.c_double, dp]
-        lib.orc_stage_coeffs.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int,
+        lib.orc_stage_matrix.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_double, dp]
+        lib.orc_stage_coeffs.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         lib.orc_evolve.argtypes = [ctypes.c_int, ip, dp, dp, dp, ctypes.c_int, dp, dp,
-                                   ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_long, dp]
         lib.orc_drift.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp]
         lib.orc_norm.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp]
@@ -75,6 +79,15 @@ def _lib():
         assert lib.orc_npar() == NPAR
         _LIB = lib
     return _LIB
+
+
+def rule_id(name: str):
+    """Rule name -> (rule number, sub-steps).  "fundamental:q" integrates each
+    stage with q sixth-order Magnus sub-steps ("fundamental": 16)."""
+    base, _, q = name.partition(":")
+    if base == "fundamental":
+        return HO_RULES[base], int(q) if q else FUNDAMENTAL_DEFAULT_SUBSTEPS
+    return HO_RULES[base], 0
 
 
 def _check(rc: int) -> None:
@@ -123,13 +136,16 @@ def scheme_coefficients(name: str):
 
 
 def params_block(inst) -> np.ndarray:
-    """Flatten an instance description into the oracle's parameter block."""
+    """Flatten an instance description into the oracle's parameter block.
+    omega[j] and sigma are (v0, amp, freq, phase[, form])."""
     p = np.zeros(NPAR)
     p[0] = inst.mu
     for j in range(3):
-        p[1 + 4 * j: 5 + 4 * j] = inst.omega[j]
+        p[1 + 4 * j: 5 + 4 * j] = inst.omega[j][:4]
+        p[36 + j] = inst.omega[j][4] if len(inst.omega[j]) > 4 else 0
         p[18 + 6 * j: 24 + 6 * j] = inst.vfac[j]
-    p[13:17] = inst.sigma
+    p[13:17] = inst.sigma[:4]
+    p[39] = inst.sigma[4] if len(inst.sigma) > 4 else 0
     p[17] = inst.eps
     return p
 
@@ -157,7 +173,7 @@ def fftn(z: np.ndarray, sign: int = -1) -> np.ndarray:
 
 def stage_matrix(inst, rule: str, axis: int, t0: float, tau: float) -> np.ndarray:
     S = np.zeros(4)
-    _check(_lib().orc_stage_matrix(HO_RULES[rule], _dp(params_block(inst)), axis, t0, tau,
+    _check(_lib().orc_stage_matrix(*rule_id(rule), _dp(params_block(inst)), axis, t0, tau,
                                    _dp(S)))
     return S.reshape(2, 2)
 
@@ -168,7 +184,7 @@ def stage_coeffs(inst, scheme: str, rule: str, dt: float, tn: float) -> np.ndarr
     a = np.array(a)
     out = np.zeros(len(a) * inst.ndim * 3)
     _check(_lib().orc_stage_coeffs(inst.ndim, _dp(params_block(inst)), len(a), _dp(a),
-                                   HO_RULES[rule], dt, tn, _dp(out)))
+                                   *rule_id(rule), dt, tn, _dp(out)))
     return out.reshape(len(a), inst.ndim, 3)
 
 
@@ -180,7 +196,7 @@ def evolve(inst, psi: np.ndarray, scheme: str, rule: str, dt: float, t0: float,
     n, lo, hi = _grid_arrays(inst)
     out = _as_c128(psi)
     _check(_lib().orc_evolve(inst.ndim, _ip(n), _dp(lo), _dp(hi), _dp(params_block(inst)),
-                             len(a), _dp(a), _dp(b), HO_RULES[rule], float(dt), float(t0),
+                             len(a), _dp(a), _dp(b), *rule_id(rule), float(dt), float(t0),
                              int(nsteps), _dp(out.view(np.float64))))
     return out
 

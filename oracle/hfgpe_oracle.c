@@ -16,8 +16,11 @@
  *   - the harmonic-oscillator stage coefficients by the "2x2 route": the
  *     classical (Heisenberg) matrix S of the stage propagator is built first
  *     (exact constant-frequency flow, the two-exponential commutator-free
- *     product of Eq. CommutatorFree, or the exponential of the sixth-order
- *     Magnus generator of Sec. 4.2) and then factored as
+ *     product of Eq. CommutatorFree, the exponential of the sixth-order
+ *     Magnus generator of Sec. 4.2, or the fundamental matrix of the stage
+ *     integrated as a product of q such Magnus steps over sub-intervals of
+ *     length tau/q -- Eq. HO(t)sol states that the exact HO flow for any
+ *     omega(t) is of this 2x2 form) and then factored as
  *     S = K(f) D(g) K(e), i.e. g = S12, e = (1-S11)/g, f = (1-S22)/g, which is
  *     the content of Lemma 2 and Theorems 1-2 (Sec. 2.2);
  *   - the Fourier split (i) of Sec. 2.1 as the comparison method: exact
@@ -37,13 +40,18 @@
  *
  * Parameter block (doubles, ORC_NPAR per instance):
  *   [0]            mu
- *   [1+4j..4+4j]   omega0, omega_amp, omega_freq, omega_phase of axis j
- *                  omega_j(t) = omega0 (1 + amp sin(freq t + phase))
- *   [13..16]       sigma0, sigma_amp, sigma_freq, sigma_phase (same form)
+ *   [1+4j..4+4j]   v0, amp, freq, phase of omega_j(t), in the form [36+j]
+ *   [13..16]       v0, amp, freq, phase of sigma(t), in the form [39]
  *   [17]           eps
  *   [18+6j..23+6j] V_I factor of axis j: c0, c2, c4, gs, k, phi
  *                  v_j(x) = (c0 + c2 x^2 + c4 x^4) * (gs > 0 ? exp(-x^2/gs) : 1)
  *                           * cos(k x + phi);   V_I = prod_j v_j(x_j)
+ *   [36+j], [39]   form of omega_j(t), sigma(t):
+ *                  0: v(t)   = v0 (1 + amp sin(freq t + phase))
+ *                  1: v(t)^2 = v0 (1 + amp sin(freq t + phase))  (the modulated
+ *                     squared frequency of the first example of Sec. 4.2)
+ *                  2: v(t)   = v0 (1 + amp t sech^2(freq (t - phase)))  (the
+ *                     short pulse of the second example of Sec. 4.2)
  *
  * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared -lm
  */
@@ -51,11 +59,11 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_NPAR 36
+#define ORC_NPAR 40
 #define ORC_PI 3.14159265358979323846
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ESINGULAR = -2, ORC_EFREQ = -3, ORC_ENOMEM = -4 };
-enum { ORC_HO_EXACT_CONST = 0, ORC_HO_CF4 = 1, ORC_HO_MAGNUS6 = 2, ORC_FSPLIT = 3 };
+enum { ORC_HO_EXACT_CONST = 0, ORC_HO_CF4 = 1, ORC_HO_MAGNUS6 = 2, ORC_FSPLIT = 3, ORC_HO_FUNDAMENTAL = 4 };
 
 /* ------------------------------------------------------------------------ */
 /* Parameter access                                                          */
@@ -63,18 +71,29 @@ enum { ORC_HO_EXACT_CONST = 0, ORC_HO_CF4 = 1, ORC_HO_MAGNUS6 = 2, ORC_FSPLIT = 
 
 static double par_mu(const double *p) { return p[0]; }
 
-/* omega_j(t) of the trap, Eq. GP1b with a time-dependent frequency. */
-static double par_omega(const double *p, int j, double t)
+/* A time-dependent coefficient in one of the three forms listed above;
+ * returns v(t) for forms 0 and 2 and v(t)^2 for form 1. */
+static double tform(const double *c, int form, double t)
 {
-    const double *w = p + 1 + 4 * j;
-    return w[0] * (1.0 + w[1] * sin(w[2] * t + w[3]));
+    if (form == 2) {
+        double sech = 1.0 / cosh(c[2] * (t - c[3]));
+        return c[0] * (1.0 + c[1] * t * sech * sech);
+    }
+    return c[0] * (1.0 + c[1] * sin(c[2] * t + c[3]));
 }
 
-/* sigma(t) of the mean-field term, Sec. 1. */
+/* omega_j(t)^2 of the trap, Eq. GP1b with a time-dependent frequency. */
+static double par_omega_sq(const double *p, int j, double t)
+{
+    int form = (int)p[36 + j];
+    double v = tform(p + 1 + 4 * j, form, t);
+    return form == 1 ? v : v * v;
+}
+
+/* sigma(t) of the mean-field term, Sec. 1 (forms 0 and 2). */
 static double par_sigma(const double *p, double t)
 {
-    const double *s = p + 13;
-    return s[0] * (1.0 + s[1] * sin(s[2] * t + s[3]));
+    return tform(p + 13, (int)p[39], t);
 }
 
 static double par_eps(const double *p) { return p[17]; }
@@ -247,10 +266,10 @@ static int ho_cf4(const double *p, int axis, double t0, double tau, double X[4])
 {
     double c1 = 0.5 - sqrt(3.0) / 6.0, c2 = 0.5 + sqrt(3.0) / 6.0;
     double al = 0.5 - 1.0 / sqrt(3.0), be = 1.0 - al;
-    double w1 = par_omega(p, axis, t0 + c1 * tau);
-    double w2 = par_omega(p, axis, t0 + c2 * tau);
-    double qL = al * w1 * w1 + be * w2 * w2;
-    double qR = be * w1 * w1 + al * w2 * w2;
+    double q1 = par_omega_sq(p, axis, t0 + c1 * tau);
+    double q2 = par_omega_sq(p, axis, t0 + c2 * tau);
+    double qL = al * q1 + be * q2;
+    double qR = be * q1 + al * q2;
     double ML[4], MR[4];
     int rc = ho_flow(qL, par_mu(p), 0.5 * tau, ML);
     if (rc) return rc;
@@ -269,10 +288,9 @@ static int ho_cf4(const double *p, int axis, double t0, double tau, double X[4])
 static int ho_magnus6(const double *p, int axis, double t0, double tau, double X[4])
 {
     double c1 = 0.5 - sqrt(15.0) / 10.0, c2 = 0.5, c3 = 0.5 + sqrt(15.0) / 10.0;
-    double a1 = par_omega(p, axis, t0 + c1 * tau);
-    double a2 = par_omega(p, axis, t0 + c2 * tau);
-    double a3 = par_omega(p, axis, t0 + c3 * tau);
-    double w1 = a1 * a1, w2 = a2 * a2, w3 = a3 * a3;
+    double w1 = par_omega_sq(p, axis, t0 + c1 * tau);
+    double w2 = par_omega_sq(p, axis, t0 + c2 * tau);
+    double w3 = par_omega_sq(p, axis, t0 + c3 * tau);
     double tt = tau * tau;
     double alpha = (5.0 * w1 + 8.0 * w2 + 5.0 * w3) / 18.0
                  + tt / 486.0 * (17.0 / 4.0 * (w1 * w1 + w3 * w3) + 8.0 * w2 * w2
@@ -296,18 +314,40 @@ static int ho_magnus6(const double *p, int axis, double t0, double tau, double X
     return ORC_OK;
 }
 
-/* Stage matrix (deviation form) for one axis over [t0, t0 + tau]. */
-static int ho_stage_matrix(int rule, const double *p, int axis, double t0, double tau, double S[4])
+/* Fundamental matrix of the stage, x' = p/mu, p' = -mu omega(t)^2 x over
+ * [t0, t0 + tau], integrated numerically: the flow over consecutive
+ * sub-intervals of length tau/q composes (later sub-intervals act last), and
+ * each sub-interval's flow is taken from the sixth-order Magnus rule above.
+ * Deviation form. */
+static int ho_fundamental(const double *p, int axis, double t0, double tau, int q, double X[4])
+{
+    if (q < 1) return ORC_EINVAL;
+    double h = tau / (double)q;
+    X[0] = X[1] = X[2] = X[3] = 0.0;
+    for (int k = 0; k < q; ++k) {
+        double A[4], Y[4];
+        int rc = ho_magnus6(p, axis, t0 + (double)k * h, h, A);
+        if (rc) return rc;
+        dev_mul(A, X, Y);
+        memcpy(X, Y, sizeof(Y));
+    }
+    return ORC_OK;
+}
+
+/* Stage matrix (deviation form) for one axis over [t0, t0 + tau]; q is the
+ * sub-step count of the fundamental-matrix rule. */
+static int ho_stage_matrix(int rule, int q, const double *p, int axis, double t0, double tau,
+                           double S[4])
 {
     switch (rule) {
-    case ORC_HO_EXACT_CONST: {
-        double w = par_omega(p, axis, t0);
-        return ho_flow(w * w, par_mu(p), tau, S);
-    }
+    case ORC_HO_EXACT_CONST:
+        return ho_flow(par_omega_sq(p, axis, t0), par_mu(p), tau, S);
     case ORC_HO_CF4:
         return ho_cf4(p, axis, t0, tau, S);
     case ORC_HO_MAGNUS6:
         return ho_magnus6(p, axis, t0, tau, S);
+    case ORC_HO_FUNDAMENTAL:
+        return ho_fundamental(p, axis, t0, tau, q, S);
     default:
         return ORC_EINVAL;
     }
@@ -328,9 +368,9 @@ static int factor_kdk(const double X[4], double *f, double *g, double *e)
 }
 
 /* Public: the 2x2 stage matrix S (not the deviation) for tests. */
-int orc_stage_matrix(int rule, const double *par, int axis, double t0, double tau, double *S)
+int orc_stage_matrix(int rule, int q, const double *par, int axis, double t0, double tau, double *S)
 {
-    int rc = ho_stage_matrix(rule, par, axis, t0, tau, S);
+    int rc = ho_stage_matrix(rule, q, par, axis, t0, tau, S);
     if (rc) return rc;
     S[0] += 1.0;
     S[3] += 1.0;
@@ -339,7 +379,7 @@ int orc_stage_matrix(int rule, const double *par, int axis, double t0, double ta
 
 /* Public: (f, g, e) of every stage and axis of the step starting at tn.
  * out[(i*ndim + j)*3 + {0,1,2}] = f, g, e of stage i, axis j. */
-int orc_stage_coeffs(int ndim, const double *par, int m, const double *a, int rule,
+int orc_stage_coeffs(int ndim, const double *par, int m, const double *a, int rule, int q,
                      double dt, double tn, double *out)
 {
     if (rule == ORC_FSPLIT) return ORC_EINVAL;
@@ -347,7 +387,7 @@ int orc_stage_coeffs(int ndim, const double *par, int m, const double *a, int ru
     for (int i = 0; i < m; ++i) {
         for (int j = 0; j < ndim; ++j) {
             double X[4];
-            int rc = ho_stage_matrix(rule, par, j, tau, a[i] * dt, X);
+            int rc = ho_stage_matrix(rule, q, par, j, tau, a[i] * dt, X);
             if (rc) return rc;
             rc = factor_kdk(X, &out[(i * ndim + j) * 3 + 0], &out[(i * ndim + j) * 3 + 1],
                             &out[(i * ndim + j) * 3 + 2]);
@@ -496,8 +536,7 @@ static void apply_B_fsplit(const grid_t *G, double *u, double dt, double w, doub
     double sig = par_sigma(G->par, tau), mu = par_mu(G->par);
     double q[3] = {0.0, 0.0, 0.0};
     for (int j = 0; j < G->ndim; ++j) {
-        double om = par_omega(G->par, j, tau);
-        q[j] = mu * om * om;
+        q[j] = mu * par_omega_sq(G->par, j, tau);
     }
     for (long idx = 0; idx < G->total; ++idx) {
         double harm = 0.0;
@@ -530,7 +569,7 @@ static int step_fsplit(const grid_t *G, double *u, int m, const double *a, const
  * "algorithm"), with each A flow replaced by its K(f) D(g) K(e) factorisation.
  * b holds m+1 weights (BAB form; b[0] = 0 gives an ABA-type scheme). */
 static int step_once(const grid_t *G, double *u, int m, const double *a, const double *b,
-                     int rule, double dt, double tn)
+                     int rule, int q, double dt, double tn)
 {
     if (rule == ORC_FSPLIT) return step_fsplit(G, u, m, a, b, dt, tn);
     double tau = tn;
@@ -539,7 +578,7 @@ static int step_once(const grid_t *G, double *u, int m, const double *a, const d
         double f[3], g[3], e[3];
         for (int j = 0; j < G->ndim; ++j) {
             double X[4];
-            int rc = ho_stage_matrix(rule, G->par, j, tau, a[i] * dt, X);
+            int rc = ho_stage_matrix(rule, q, G->par, j, tau, a[i] * dt, X);
             if (rc) return rc;
             rc = factor_kdk(X, &f[j], &g[j], &e[j]);
             if (rc) return rc;
@@ -557,7 +596,7 @@ static int step_once(const grid_t *G, double *u, int m, const double *a, const d
 /* Public: evolve one instance nsteps steps from t0.  psi is interleaved
  * complex (re, im) in row-major order with x fastest. */
 int orc_evolve(int ndim, const int *n, const double *lo, const double *hi, const double *par,
-               int m, const double *a, const double *b, int rule, double dt, double t0,
+               int m, const double *a, const double *b, int rule, int q, double dt, double t0,
                long nsteps, double *psi)
 {
     if (m < 1 || nsteps < 0) return ORC_EINVAL;
@@ -565,7 +604,7 @@ int orc_evolve(int ndim, const int *n, const double *lo, const double *hi, const
     int rc = grid_init(&G, ndim, n, lo, hi, par);
     if (rc) { grid_free(&G); return rc; }
     for (long s = 0; s < nsteps && rc == ORC_OK; ++s)
-        rc = step_once(&G, psi, m, a, b, rule, dt, t0 + (double)s * dt);
+        rc = step_once(&G, psi, m, a, b, rule, q, dt, t0 + (double)s * dt);
     grid_free(&G);
     return rc;
 }
@@ -627,9 +666,8 @@ int orc_energy(int ndim, const int *n, const double *lo, const double *hi, const
         double k2h = 0.0, vh = 0.0;
         for (int j = 0; j < ndim; ++j) {
             long i = axis_index(&G, idx, j);
-            double w = par_omega(par, j, t);
             k2h += axis_table(&G, G.k2h, j)[i];
-            vh += mu * w * w * axis_table(&G, G.x2h, j)[i];
+            vh += mu * par_omega_sq(par, j, t) * axis_table(&G, G.x2h, j)[i];
         }
         double a2h = uh[2 * idx] * uh[2 * idx] + uh[2 * idx + 1] * uh[2 * idx + 1];
         ksum_add(&kin, k2h / mu * a2h);

@@ -21,7 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhfgpe.so")
 
 HFGPE_C64, HFGPE_C128 = 0, 1
-HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2, "fsplit": 3}
+HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2, "fsplit": 3, "fundamental": 4}
+TF_KINDS = {"sin": 0, "sq_sin": 1, "pulse": 2}
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "singular stage",
           -4: "non-positive frequency", -5: "allocation failed", -6: "HIP error",
           -7: "non-finite coefficient", -8: "no gfx950 device"}
@@ -42,9 +43,9 @@ class Grid(ctypes.Structure):
                 ("hi", ctypes.c_double * 3)]
 
 
-class SinMod(ctypes.Structure):
+class TFunc(ctypes.Structure):
     _fields_ = [("v0", ctypes.c_double), ("amp", ctypes.c_double), ("freq", ctypes.c_double),
-                ("phase", ctypes.c_double)]
+                ("phase", ctypes.c_double), ("kind", ctypes.c_int)]
 
 
 class VFactor(ctypes.Structure):
@@ -52,13 +53,21 @@ class VFactor(ctypes.Structure):
 
 
 class Params(ctypes.Structure):
-    _fields_ = [("mu", ctypes.c_double), ("omega", SinMod * 3), ("sigma", SinMod),
+    _fields_ = [("mu", ctypes.c_double), ("omega", TFunc * 3), ("sigma", TFunc),
                 ("eps", ctypes.c_double), ("v", VFactor * 3)]
 
 
 class Scheme(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int), ("a", ctypes.POINTER(ctypes.c_double)),
-                ("b", ctypes.POINTER(ctypes.c_double)), ("ho_rule", ctypes.c_int)]
+                ("b", ctypes.POINTER(ctypes.c_double)), ("ho_rule", ctypes.c_int),
+                ("ho_substeps", ctypes.c_int)]
+
+
+def parse_rule(name: str):
+    """HO rule name -> (hfgpe_ho_rule, ho_substeps).  "fundamental:q" selects
+    q Magnus sub-steps per stage ("fundamental" alone: the library default)."""
+    base, _, q = name.partition(":")
+    return HO_RULES[base], int(q) if q else 0
 
 
 class Options(ctypes.Structure):
@@ -122,7 +131,7 @@ def stage_coeffs_params(inst, scheme: str, ho_rule: str, dt: float, tn: float) -
     lib = load()
     a, b = scheme_preset(scheme)
     ca, cb = (ctypes.c_double * len(a))(*a), (ctypes.c_double * len(b))(*b)
-    sch = Scheme(len(a), ca, cb, HO_RULES[ho_rule])
+    sch = Scheme(len(a), ca, cb, *parse_rule(ho_rule))
     out = (ctypes.c_double * (len(a) * inst.ndim * 3))()
     p = make_params(inst)
     _check(lib.hfgpe_stage_coeffs_params(ctypes.byref(p), inst.ndim, ctypes.byref(sch), float(dt),
@@ -140,13 +149,19 @@ def make_grid(inst) -> Grid:
     return g
 
 
+def make_tfunc(spec) -> TFunc:
+    """(v0, amp, freq, phase[, kind]) -> hfgpe_tfunc (kind 0 when omitted)."""
+    kind = int(spec[4]) if len(spec) > 4 else 0
+    return TFunc(*[float(v) for v in spec[:4]], kind)
+
+
 def make_params(inst) -> Params:
     p = Params()
     p.mu = float(inst.mu)
     for j in range(3):
-        p.omega[j] = SinMod(*[float(v) for v in inst.omega[j]])
+        p.omega[j] = make_tfunc(inst.omega[j])
         p.v[j] = VFactor(*[float(v) for v in inst.vfac[j]])
-    p.sigma = SinMod(*[float(v) for v in inst.sigma])
+    p.sigma = make_tfunc(inst.sigma)
     p.eps = float(inst.eps)
     return p
 
@@ -168,7 +183,7 @@ class Plan:
             a, b = scheme_preset(scheme)
         self._a = (ctypes.c_double * len(a))(*a)
         self._b = (ctypes.c_double * len(b))(*b)
-        sch = Scheme(len(a), self._a, self._b, HO_RULES[ho_rule])
+        sch = Scheme(len(a), self._a, self._b, *parse_rule(ho_rule))
         grids = (Grid * max(1, self.n_inst))(*[make_grid(i) for i in instances])
         params = (Params * max(1, self.n_inst))(*[make_params(i) for i in instances])
         opts = Options(int(steps_per_launch), int(bool(plain)), int(bool(use_graph)),

@@ -124,21 +124,82 @@ struct hfgpe_plan {
 
 namespace {
 
-SinMod to_sm(const hfgpe_sinmod &s) { return SinMod{s.v0, s.amp, s.freq, s.phase}; }
+TFunc to_tf(const hfgpe_tfunc &s)
+{
+    TFunc t;
+    t.v0 = s.v0;
+    t.amp = s.amp;
+    t.freq = s.freq;
+    t.phase = s.phase;
+    t.kind = s.kind;
+    t.pad_ = 0;
+    return t;
+}
+
+bool tf_ok(const hfgpe_tfunc &s, bool frequency)
+{
+    if (!std::isfinite(s.v0) || !std::isfinite(s.amp) || !std::isfinite(s.freq) || !std::isfinite(s.phase))
+        return false;
+    if (s.kind == HFGPE_TF_SIN) return true;
+    if (s.kind == HFGPE_TF_SQ_SIN) return frequency;
+    if (s.kind == HFGPE_TF_PULSE) return s.amp == 0.0 || s.freq != 0.0;
+    return false;
+}
+
+// Range [qmin, qmax] of omega(t)^2 over all t, and a time window whose
+// sampling shows the modulation (one period, or the pulse +- 10 widths).
+void tf_square_range(const hfgpe_tfunc &w, double &qmin, double &qmax, double &t0, double &t1)
+{
+    t0 = t1 = 0.0;
+    if (w.amp == 0.0) {
+        qmin = qmax = (w.kind == HFGPE_TF_SQ_SIN) ? w.v0 : w.v0 * w.v0;
+        return;
+    }
+    if (w.kind == HFGPE_TF_PULSE) {
+        // h(t) = t / cosh^2(B (t - c)) vanishes at t = 0 and for |t| -> inf;
+        // its extremes lie within 30 widths of the centre: dense sampling,
+        // widened by 1% of the range
+        const double B = std::fabs(w.freq), c = w.phase;
+        double hmin = 0.0, hmax = 0.0;
+        for (int k = 0; k <= 16384; ++k) {
+            double t = c + (60.0 * k / 16384.0 - 30.0) / B;
+            double ch = std::cosh(B * (t - c));
+            double h = t / (ch * ch);
+            hmin = std::min(hmin, h);
+            hmax = std::max(hmax, h);
+        }
+        const double pad = 0.01 * (hmax - hmin);
+        hmin -= pad;
+        hmax += pad;
+        double v1 = w.v0 * (1.0 + w.amp * hmin), v2 = w.v0 * (1.0 + w.amp * hmax);
+        double lo = std::min(v1, v2), hi = std::max(v1, v2);
+        qmin = (lo > 0.0) ? lo * lo : -1.0;
+        qmax = hi * hi;
+        t0 = c - 10.0 / B;
+        t1 = c + 10.0 / B;
+        return;
+    }
+    double lo = w.v0 * (1.0 - std::fabs(w.amp)), hi = w.v0 * (1.0 + std::fabs(w.amp));
+    if (w.kind == HFGPE_TF_SQ_SIN) {
+        qmin = lo;
+        qmax = hi;
+    } else {
+        qmin = (lo > 0.0) ? lo * lo : -1.0;
+        qmax = hi * hi;
+    }
+    if (w.freq != 0.0) t1 = 2.0 * M_PI / std::fabs(w.freq);
+}
 
 // Conservative host-side validity check of every stage for the frequency
-// range an instance can reach, then a sampled check of the exact closed
-// forms over one modulation period.
+// range an instance can reach, then a sampled check of the coefficients over
+// the modulation window.
 int validate_instance(const hfgpe_params &p, int nd, const SchemeDev &S, double dt)
 {
     if (!(p.mu > 0.0) || !std::isfinite(p.mu)) return HFGPE_E_INVALID_ARG;
     if (!std::isfinite(p.eps)) return HFGPE_E_INVALID_ARG;
-    const hfgpe_sinmod *sm[4] = {&p.omega[0], &p.omega[1], &p.omega[2], &p.sigma};
-    for (int j = 0; j < 4; ++j) {
-        const hfgpe_sinmod &s = *sm[j];
-        if (!std::isfinite(s.v0) || !std::isfinite(s.amp) || !std::isfinite(s.freq) || !std::isfinite(s.phase))
-            return HFGPE_E_INVALID_ARG;
-    }
+    for (int j = 0; j < 3; ++j)
+        if (!tf_ok(p.omega[j], true)) return HFGPE_E_INVALID_ARG;
+    if (!tf_ok(p.sigma, false)) return HFGPE_E_INVALID_ARG;
     for (int j = 0; j < 3; ++j) {
         const hfgpe_vfactor &v = p.v[j];
         if (!std::isfinite(v.c0) || !std::isfinite(v.c2) || !std::isfinite(v.c4) || !std::isfinite(v.gs) ||
@@ -149,30 +210,32 @@ int validate_instance(const hfgpe_params &p, int nd, const SchemeDev &S, double 
     double amax = 0.0;
     for (int i = 0; i < S.m; ++i) amax = std::max(amax, std::fabs(S.a[i]));
     for (int j = 0; j < nd; ++j) {
-        const hfgpe_sinmod &w = p.omega[j];
-        double wmin = w.v0 * (1.0 - std::fabs(w.amp)), wmax = w.v0 * (1.0 + std::fabs(w.amp));
-        if (!(w.v0 > 0.0) || !(wmin > 0.0)) return HFGPE_E_NONPOSITIVE_FREQ;
+        const hfgpe_tfunc &w = p.omega[j];
+        double qmin, qmax, win0, win1;
+        tf_square_range(w, qmin, qmax, win0, win1);
+        if (!(w.v0 > 0.0) || !(qmin > 0.0)) return HFGPE_E_NONPOSITIVE_FREQ;
+        const double wmax = std::sqrt(qmax);
         if (S.rule == HFGPE_HO_EXACT_CONST) {
             if (w.amp != 0.0) return HFGPE_E_INVALID_ARG;
-            if (!(w.v0 * amax * std::fabs(dt) < M_PI)) return HFGPE_E_SINGULAR;
+            if (!(wmax * amax * std::fabs(dt) < M_PI)) return HFGPE_E_SINGULAR;
+        } else if (S.rule == HFGPE_HO_FUNDAMENTAL) {
+            if (!(wmax * amax * std::fabs(dt) < M_PI)) return HFGPE_E_SINGULAR;
         } else {
-            // alpha w_max^2 + beta w_min^2 > 0 keeps omega_L^2, omega_R^2 > 0
+            // alpha q_max + beta q_min > 0 keeps omega_L^2, omega_R^2 > 0
             const double al = 0.5 - 1.0 / std::sqrt(3.0), be = 1.0 - al;
-            if (S.rule == HFGPE_HO_CF4 && !(al * wmax * wmax + be * wmin * wmin > 0.0))
-                return HFGPE_E_NONPOSITIVE_FREQ;
+            if (S.rule == HFGPE_HO_CF4 && !(al * qmax + be * qmin > 0.0)) return HFGPE_E_NONPOSITIVE_FREQ;
             if (!(std::sqrt(be) * wmax * amax * std::fabs(dt) < M_PI)) return HFGPE_E_SINGULAR;
         }
-        // sampled check of the closed forms over one period of omega(t)
-        double period = (w.freq != 0.0 && w.amp != 0.0) ? 2.0 * M_PI / std::fabs(w.freq) : 0.0;
-        SinMod om = to_sm(w);
+        // sampled check of the stage coefficients over the modulation window
+        const TFunc om = to_tf(w);
         for (int k = 0; k < 64; ++k) {
-            double t = period * k / 64.0;
+            double t = win0 + (win1 - win0) * k / 64.0;
             for (int i = 0; i < S.m; ++i) {
-                Fge q = fge_stage(S.rule, p.mu, om, t, dt * S.a[i]);
+                Fge q = fge_stage(S.rule, p.mu, om, t, dt * S.a[i], S.substeps);
                 if (q.status) return q.status;
                 if (!std::isfinite(q.f) || !std::isfinite(q.g) || !std::isfinite(q.e)) return HFGPE_E_NONFINITE;
             }
-            if (period == 0.0) break;
+            if (win1 == win0) break;
         }
     }
     return HFGPE_OK;
@@ -181,11 +244,13 @@ int validate_instance(const hfgpe_params &p, int nd, const SchemeDev &S, double 
 int build_scheme(const hfgpe_scheme *s, int nd, SchemeDev &S)
 {
     if (!s || !s->a || !s->b || s->m < 1 || s->m > kMaxStages) return HFGPE_E_INVALID_ARG;
-    if (s->ho_rule < HFGPE_HO_EXACT_CONST || s->ho_rule > HFGPE_FSPLIT) return HFGPE_E_INVALID_ARG;
+    if (s->ho_rule < HFGPE_HO_EXACT_CONST || s->ho_rule > HFGPE_HO_FUNDAMENTAL) return HFGPE_E_INVALID_ARG;
+    if (s->ho_substeps < 0 || s->ho_substeps > HFGPE_MAX_HO_SUBSTEPS) return HFGPE_E_INVALID_ARG;
     std::memset(&S, 0, sizeof(S));
     S.m = s->m;
     S.rule = (int)s->ho_rule;
     S.ndim = nd;
+    S.substeps = s->ho_substeps ? s->ho_substeps : 16;
     double c = 0.0;
     for (int i = 0; i < s->m; ++i) {
         if (!std::isfinite(s->a[i]) || s->a[i] == 0.0) return HFGPE_E_INVALID_ARG;
@@ -494,13 +559,13 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
             double L = (j < nd) ? (g.hi[j] - g.lo[j]) : 1.0;
             I.dx[j] = L / (double)I.n[j];
             I.kscale[j] = 2.0 * M_PI / L;
-            I.om[j] = to_sm(p.omega[j]);
+            I.om[j] = to_tf(p.omega[j]);
             I.vf[j] = VFac{p.v[j].c0, p.v[j].c2, p.v[j].c4, p.v[j].gs, p.v[j].k, p.v[j].phi};
             pts *= I.n[j];
         }
         I.mu = p.mu;
         I.eps = p.eps;
-        I.sig = to_sm(p.sigma);
+        I.sig = to_tf(p.sigma);
         P->offsets[k] = off;
         off += pts;
     }
@@ -838,7 +903,7 @@ int hfgpe_stage_coeffs(const hfgpe_plan *P, int inst, double tn, double *out)
     for (int i = 0; i < S.m; ++i) {
         double tau = tn + P->dt * S.cum[i];
         for (int j = 0; j < I.ndim; ++j) {
-            Fge q = fge_stage(S.rule, I.mu, I.om[j], tau, P->dt * S.a[i]);
+            Fge q = fge_stage(S.rule, I.mu, I.om[j], tau, P->dt * S.a[i], S.substeps);
             if (q.status) return q.status;
             out[(i * I.ndim + j) * 3 + 0] = q.f;
             out[(i * I.ndim + j) * 3 + 1] = q.g;
@@ -858,7 +923,7 @@ int hfgpe_stage_coeffs_params(const hfgpe_params *params, int ndim, const hfgpe_
     for (int i = 0; i < S.m; ++i) {
         double tau = tn + dt * S.cum[i];
         for (int j = 0; j < ndim; ++j) {
-            Fge q = fge_stage(S.rule, params->mu, to_sm(params->omega[j]), tau, dt * S.a[i]);
+            Fge q = fge_stage(S.rule, params->mu, to_tf(params->omega[j]), tau, dt * S.a[i], S.substeps);
             if (q.status) return q.status;
             out[(i * ndim + j) * 3 + 0] = q.f;
             out[(i * ndim + j) * 3 + 1] = q.g;

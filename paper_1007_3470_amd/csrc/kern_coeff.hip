@@ -46,7 +46,7 @@ __global__ void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
     Rec *out = rec + ((size_t)inst * k_steps + s) * m;
     Fge cur[3];
     for (int j = 0; j < nd; ++j) {
-        cur[j] = fge_stage(rule, I.mu, I.om[j], tn, dt * sch->a[0]);
+        cur[j] = fge_stage(rule, I.mu, I.om[j], tn, dt * sch->a[0], sch->substeps);
         raise_err(err, cur[j].status);
     }
     if (n == 0) {
@@ -56,12 +56,9 @@ __global__ void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
             o.chi[j] = (j < nd) ? cur[j].e : 0.0;
         }
         o.w = dt * sch->b[0];
-        o.s = o.w * sinmod(I.sig, tn);
+        o.s = o.w * tf_value(I.sig, tn);
         if (rule == 3)
-            for (int j = 0; j < nd; ++j) {
-                const double om = sinmod(I.om[j], tn);
-                o.chi[j] += o.w * I.mu * om * om;
-            }
+            for (int j = 0; j < nd; ++j) o.chi[j] += o.w * I.mu * tf_square(I.om[j], tn);
         rec_open[inst] = o;
     }
     for (int i = 0; i < m; ++i) {
@@ -75,7 +72,7 @@ __global__ void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
         if (i < m - 1) {
             tau_next = tn + dt * sch->cum[i + 1];
             for (int j = 0; j < nd; ++j) {
-                cur[j] = fge_stage(rule, I.mu, I.om[j], tau_next, dt * sch->a[i + 1]);
+                cur[j] = fge_stage(rule, I.mu, I.om[j], tau_next, dt * sch->a[i + 1], sch->substeps);
                 raise_err(err, cur[j].status);
                 r.chi[j] = fprev[j] + cur[j].e;
             }
@@ -83,7 +80,7 @@ __global__ void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
         } else if (!last) {
             tau_next = tn1;
             for (int j = 0; j < nd; ++j) {
-                Fge q = fge_stage(rule, I.mu, I.om[j], tn1, dt * sch->a[0]);
+                Fge q = fge_stage(rule, I.mu, I.om[j], tn1, dt * sch->a[0], sch->substeps);
                 raise_err(err, q.status);
                 r.chi[j] = fprev[j] + q.e;
             }
@@ -93,12 +90,9 @@ __global__ void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
             for (int j = 0; j < nd; ++j) r.chi[j] = fprev[j];
             r.w = dt * sch->b[m];
         }
-        r.s = r.w * sinmod(I.sig, tau_next);
+        r.s = r.w * tf_value(I.sig, tau_next);
         if (rule == 3)  // Fourier split: the harmonic potential is part of B
-            for (int j = 0; j < nd; ++j) {
-                const double om = sinmod(I.om[j], tau_next);
-                r.chi[j] += r.w * I.mu * om * om;
-            }
+            for (int j = 0; j < nd; ++j) r.chi[j] += r.w * I.mu * tf_square(I.om[j], tau_next);
         bool finite = isfinite(r.w) && isfinite(r.s);
         for (int j = 0; j < 3; ++j) finite = finite && isfinite(r.g[j]) && isfinite(r.chi[j]);
         if (!finite) raise_err(err, -7);

@@ -40,10 +40,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(const InstDev *__restrict__
     const Store *u = psi + I.offset;
     double hw[3];  // mu omega_j(t)^2 / 2
     for (int j = 0; j < 3; ++j) {
-        double w = sinmod(I.om[j], t);
-        hw[j] = (j < nd) ? 0.5 * I.mu * w * w : 0.0;
+        hw[j] = (j < nd) ? 0.5 * I.mu * tf_square(I.om[j], t) : 0.0;
     }
-    const double sig = sinmod(I.sig, t);
+    const double sig = tf_value(I.sig, t);
     Ksum a, b, c;
     for (int64_t idx = (int64_t)blk * 256 + threadIdx.x; idx < total; idx += (int64_t)nblk * 256) {
         double re = (double)u[idx].x, im = (double)u[idx].y;

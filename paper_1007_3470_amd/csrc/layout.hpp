@@ -10,8 +10,12 @@ namespace hfgpe {
 
 constexpr int kMaxStages = 16;
 
-struct SinMod {
-    double v0, amp, freq, phase;  // v(t) = v0 (1 + amp sin(freq t + phase))
+// A time-dependent coefficient (omega_j or sigma); kind 0: v = v0 (1 + amp sin(freq t + phase));
+// 1: v^2 = v0 (1 + amp sin(freq t + phase)); 2: v = v0 (1 + amp t / cosh^2(freq (t - phase))).
+struct TFunc {
+    double v0, amp, freq, phase;
+    int kind;
+    int pad_;
 };
 
 struct VFac {
@@ -30,8 +34,8 @@ struct InstDev {
     double kscale[3];  // 2 pi / L_j
     double mu;
     double eps;
-    SinMod om[3];
-    SinMod sig;
+    TFunc om[3];
+    TFunc sig;
     VFac vf[3];
 };
 
@@ -53,7 +57,7 @@ struct SchemeDev {
     int m;
     int rule;
     int ndim;
-    int pad_;
+    int substeps;  // Magnus sub-steps per stage of the fundamental-matrix rule
     double a[kMaxStages];
     double b[kMaxStages + 1];
     double cum[kMaxStages + 1];

@@ -75,12 +75,68 @@ def test_closed_forms_match_oracle_matrix_route(rule, scheme, dt):
         assert np.allclose(lib_c, orc_c, rtol=1e-12, atol=0), np.abs(lib_c / orc_c - 1).max()
 
 
+FORMS = {"sin": (1.4, 0.3, 3.0, 0.2, 0), "sq_sin": W.TIMEDEP_OMEGA["cos"],
+         "pulse": W.TIMEDEP_OMEGA["pulse"]}
+
+
+@pytest.mark.parametrize("form", sorted(FORMS))
+@pytest.mark.parametrize("rule", ["cf4", "magnus6", "fundamental", "fundamental:5", "fsplit"])
+@pytest.mark.parametrize("scheme,dt", [("leapfrog", 0.05), ("ni5_84", -0.03), ("srkn6_4", 0.1)])
+def test_time_forms_and_fundamental_rule_match_oracle(form, rule, scheme, dt):
+    """The library's (f, g, e) under the trap forms of Sec. 4.2 and the
+    fundamental-matrix rule agree with the oracle's 2x2 route."""
+    for mu, tn in ((1.0, 0.0), (1.7, 1.85), (0.6, 2.3)):
+        inst = W.Instance(1, (8, 1, 1), (-1, 0, 0), (1, 1, 1), mu=mu,
+                          omega=(FORMS[form], W.CONST_OMEGA, W.CONST_OMEGA))
+        lib_c = pkg.stage_coeffs_params(inst, scheme, rule, dt, tn)
+        if rule == "fsplit":   # free drift: g = a_i dt / mu, no chirps
+            a, _ = oracle.scheme_coefficients(scheme)
+            assert np.allclose(lib_c[:, 0, 1], np.array(a) * dt / mu, rtol=1e-15, atol=0)
+            assert not lib_c[:, 0, 0].any() and not lib_c[:, 0, 2].any()
+            continue
+        orc_c = oracle.stage_coeffs(inst, scheme, rule, dt, tn)
+        assert np.allclose(lib_c, orc_c, rtol=1e-12, atol=0), np.abs(lib_c / orc_c - 1).max()
+
+
+def test_time_form_validation():
+    base = W.gpe_1d(n=64, nsteps=0).instances[0]
+    pulse = replace(base, omega=(W.TIMEDEP_OMEGA["pulse"],) + base.omega[1:])
+    cosq = replace(base, omega=(W.TIMEDEP_OMEGA["cos"],) + base.omega[1:])
+    for inst in (pulse, cosq):
+        for rule in ("cf4", "magnus6", "fundamental", "fsplit"):
+            assert _gpu_or_nodevice(_create([inst], rule=rule, dt=1e-2)), rule
+    assert _create([replace(base, sigma=(1.0, 0.1, 1.0, 0.0, 1))]) == -1     # sigma: no squared form
+    assert _gpu_or_nodevice(_create([replace(base, sigma=(1.0, 0.1, 1.0, 0.0, 2))]))
+    assert _create([replace(base, omega=((4.0, 0.2, 0.0, 2.0, 2),) + base.omega[1:])]) == -1
+    assert _create([replace(base, omega=((1.0, 0.0, 0.0, 0.0, 7),) + base.omega[1:])]) == -1
+    # pulse driving omega through zero: 1 - 2 * max|t sech^2| < 0
+    neg = replace(base, omega=((4.0, -2.0, 2.0, 2.0, 2),) + base.omega[1:])
+    assert _create([neg]) == -4
+    assert _create([replace(base, omega=((1.0, 1.2, 1.0, 0.0, 1),) + base.omega[1:])]) == -4
+    # constant squared form is a constant frequency sqrt(v0) for the exact rule
+    const_sq = replace(base, omega=((2.25, 0.0, 0.0, 0.0, 1),) + base.omega[1:])
+    assert _gpu_or_nodevice(_create([const_sq], rule="exact_const", dt=2.0))   # 1.5 * 2 < pi
+    assert _create([const_sq], rule="exact_const", dt=2.2) == -3              # 1.5 * 2.2 > pi
+    assert _create([pulse], rule="exact_const") == -1
+    assert _gpu_or_nodevice(_create([pulse], rule="fundamental:256", dt=1e-2))
+    assert _create([pulse], rule="fundamental:257", dt=1e-2) == -1
+
+
+def test_exact_const_matches_oracle_for_constant_squared_form():
+    inst = W.Instance(1, (8, 1, 1), (-1, 0, 0), (1, 1, 1), mu=1.3,
+                      omega=((2.25, 0.0, 0.0, 0.0, 1), W.CONST_OMEGA, W.CONST_OMEGA))
+    lib_c = pkg.stage_coeffs_params(inst, "leapfrog", "exact_const", 0.7, 0.0)
+    mu, w, t = 1.3, 1.5, 0.7
+    assert np.allclose(lib_c[0, 0], [mu * w * math.tan(w * t / 2), math.sin(w * t) / (mu * w),
+                                     mu * w * math.tan(w * t / 2)], rtol=1e-14, atol=0)
+
+
 def _create(instances, scheme="leapfrog", rule="cf4", dtype=1, dt=1e-3, m=None, a=None, b=None):
     lib = pkg.load()
     if a is None:
         a, b = pkg.scheme_preset(scheme)
     ca, cb = (ctypes.c_double * len(a))(*a), (ctypes.c_double * len(b))(*b)
-    sch = pkg.Scheme(len(a) if m is None else m, ca, cb, pkg.HO_RULES[rule])
+    sch = pkg.Scheme(len(a) if m is None else m, ca, cb, *pkg.parse_rule(rule))
     n = len(instances)
     g = (pkg.Grid * max(1, n))(*[pkg.make_grid(i) for i in instances])
     p = (pkg.Params * max(1, n))(*[pkg.make_params(i) for i in instances])

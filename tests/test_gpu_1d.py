@@ -230,3 +230,42 @@ def test_fourier_split_1d(pkg, scheme, dtype):
         err = W.rel_l2(got[k], oracle_run(w, k))
         say("fsplit %s %s k=%d rel_l2 %.3e" % (scheme, dtype, k, err))
         assert err < TOL[dtype]
+
+
+# ---------------------------------------------------------------------------
+# time-dependent traps of Sec. 4.2 and the fundamental-matrix rule
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["cos", "pulse"])
+@pytest.mark.parametrize("rule", ["cf4", "magnus6", "fundamental", "fundamental:3", "fsplit"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_timedep_traps_1d(pkg, form, rule, dtype):
+    # 0.5 time units across the pulse centre (t = 2) with a fourth-order scheme
+    w = W.timedep_1d(form=form, n=1024, T=0.5, nsteps=50, scheme="srkn6_4", rule=rule)
+    w = replace(w, t0=1.8)
+    _, _, got = run_gpu(pkg, w, dtype)
+    err = W.rel_l2(got[0], oracle_run(w, 0))
+    say("timedep %s %s %s rel_l2 %.3e" % (form, rule, dtype, err))
+    assert err < TOL[dtype]
+
+
+@pytest.mark.parametrize("sigma", [0.01, 1.0, 100.0])
+@pytest.mark.parametrize("rule", ["exact_const", "fsplit"])
+def test_perturbed_problem_1d(pkg, sigma, rule):
+    w = W.perturbed_1d(sigma=sigma, T=0.4, nsteps=40, scheme="ni4_82", rule=rule)
+    _, _, got = run_gpu(pkg, w, "c128")
+    err = W.rel_l2(got[0], oracle_run(w, 0))
+    say("perturbed sigma=%g %s rel_l2 %.3e" % (sigma, rule, err))
+    assert err < 1e-11
+
+
+def test_fundamental_rule_batch_mixed_forms(pkg):
+    """A batch whose instances use all three time forms, fundamental rule."""
+    base = W.batch_1d(n_inst=6, sizes=(256, 512, 2048), nsteps=30, seed=5, rule="fundamental:8")
+    forms = [(1.2, 0.3, 2.0, 0.1, 0), W.TIMEDEP_OMEGA["cos"], W.TIMEDEP_OMEGA["pulse"]]
+    insts = [replace(inst, omega=(forms[k % 3],) + inst.omega[1:]) for k, inst in enumerate(base.instances)]
+    w = replace(base, instances=insts, t0=1.9)
+    _, _, got = run_gpu(pkg, w, "c128")
+    for k in range(len(insts)):
+        err = W.rel_l2(got[k], oracle_run(w, k))
+        say("fundamental batch k=%d rel_l2 %.3e" % (k, err))
+        assert err < 1e-11

@@ -210,3 +210,24 @@ def test_fourier_split_nd(pkg, dtype):
             err = W.rel_l2(got[k], ref)
             say("fsplit %dD %s k=%d rel_l2 %.3e" % (inst.ndim, dtype, k, err))
             assert err < TOL[dtype]
+
+
+@pytest.mark.parametrize("rule", ["fundamental", "magnus6"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_nd_time_forms(pkg, rule, dtype):
+    """2-D and 3-D grids with the Sec. 4.2 trap forms on different axes."""
+    w2 = W.gpe_2d(n=64, n_inst=2, nsteps=12, rule=rule, dt=2e-3)
+    insts = [replace(i, omega=(W.TIMEDEP_OMEGA["pulse"], W.TIMEDEP_OMEGA["cos"], W.CONST_OMEGA),
+                     sigma=(5.0, 0.5, 3.0, 0.0, 2)) for i in w2.instances]
+    w2 = replace(w2, instances=insts, t0=1.95)
+    w3 = W.gpe_3d(n=32, nsteps=3, rule=rule)
+    i3 = replace(w3.instances[0], omega=(W.TIMEDEP_OMEGA["cos"], (1.2, 0.2, 1.3, 0.0),
+                                         W.TIMEDEP_OMEGA["pulse"]))
+    w3 = replace(w3, instances=[i3], t0=1.99)
+    for w in (w2, w3):
+        _, _, got = run_gpu(pkg, w, dtype)
+        for k, inst in enumerate(w.instances):
+            ref = oracle.evolve(inst, w.psi0[k], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
+            err = W.rel_l2(got[k], ref)
+            say("nd forms %dD %s %s k=%d rel_l2 %.3e" % (inst.ndim, rule, dtype, k, err))
+            assert err < TOL[dtype]

@@ -7,9 +7,10 @@ library's tests/benchmark and the CPU oracle start from the bytes it produces.
 Physics (Sec. 1 of the paper, Eq. GP1 generalised to d dimensions):
     i psi_t = ( p^2/(2 mu) + sum_j mu omega_j(t)^2 x_j^2 / 2
                 + eps V_I(x) + sigma(t) |psi|^2 ) psi
-with
-    omega_j(t) = omega0_j (1 + amp_j sin(freq_j t + phase_j))
-    sigma(t)   = sigma0   (1 + amp   sin(freq   t + phase  ))
+with omega_j(t) and sigma(t) given as (v0, amp, freq, phase[, form]):
+    form 0 (default)  v(t)   = v0 (1 + amp sin(freq t + phase))
+    form 1            v(t)^2 = v0 (1 + amp sin(freq t + phase))   (omega only)
+    form 2            v(t)   = v0 (1 + amp t / cosh^2(freq (t - phase)))
     V_I(x)     = prod_j (c0 + c2 x_j^2 + c4 x_j^4) exp(-x_j^2/gs) cos(k x_j + phi)
                  (the Gaussian factor is dropped when gs == 0).
 Grid: x_{j,i} = lo_j + i (hi_j - lo_j)/n_j, periodic, arrays stored with x
@@ -17,8 +18,11 @@ fastest (numpy shape (nz, ny, nx) / (ny, nx) / (nx,)).
 
 Workloads follow the five benchmark configurations of the project: a 1-D
 coherent state, a 1-D GPE with a time-dependent trap, a heterogeneous batch of
-4096 1-D GPEs, 16 anisotropic 2-D GPEs and one 3-D GPE.  Every generator takes
-size overrides so tests can run the same recipe at small sizes.
+4096 1-D GPEs, 16 anisotropic 2-D GPEs and one 3-D GPE.  Two more recipes
+follow the paper's own numerical examples: the weakly to strongly nonlinear
+problem of Sec. 4.1 (Figs. 2-6) and the time-dependent traps with a quartic
+perturbation of Sec. 4.2 (Figs. 7-8).  Every generator takes size overrides so
+tests can run the same recipe at small sizes.
 """
 from __future__ import annotations
 
@@ -202,12 +206,54 @@ def gpe_3d(n: int = 256, lo: float = -8.0, hi: float = 8.0, dt: float = 1e-3,
                     rule, dt, nsteps, notes="%d^3 on [%g,%g)^3, seed %d" % (n, lo, hi, seed))
 
 
+# ---------------------------------------------------------------------------
+# Sec. 4.1 (Figs. 2-6): mu = omega = 1, V_I = 0, sigma in {0.01, 1, 100},
+# psi(x, 0) = rho exp(-(x-1)^2/2); [-20, 20] for sigma = 0.01, [-30, 30] else.
+# The figures (absent) hold N and T; N = 1024 and T = 10 are this recipe's.
+# ---------------------------------------------------------------------------
+def perturbed_1d(sigma: float = 1.0, n: int = 1024, T: float = 10.0, nsteps: int = 1000,
+                 scheme: str = "leapfrog", rule: str = "exact_const") -> Workload:
+    L = 20.0 if sigma < 0.1 else 30.0
+    inst = Instance(1, *_grid1(n, -L, L), sigma=(float(sigma), 0.0, 0.0, 0.0))
+    x = inst.axis(0)
+    psi = _normalise(inst, np.exp(-(x - 1.0) ** 2 / 2.0).astype(np.complex128))
+    return Workload("perturbed_1d", [inst], [psi], scheme, rule, T / nsteps, nsteps,
+                    notes="sigma=%g, N=%d on [%g,%g), T=%g" % (sigma, n, -L, L, T))
+
+
+# ---------------------------------------------------------------------------
+# Sec. 4.2 (Figs. 7-8): linear HO with a time-dependent frequency plus the
+# static quartic eps_Q x^4/4, eps_Q = 0.01, on [-20, 20]:
+#   "cos":   omega^2(t) = 4 (1 + 0.1 cos(t/2))        (form 1, phase pi/2)
+#   "pulse": omega(t) = 4 (1 + 0.25 t / cosh^2(2 (t - 2)))   (form 2)
+# The paper states neither the initial state nor T nor N; this recipe takes
+# the Sec. 4.1 state exp(-(x-1)^2/2), T = 5 and N = 1024.
+# ---------------------------------------------------------------------------
+TIMEDEP_OMEGA = {
+    "cos": (4.0, 0.1, 0.5, math.pi / 2.0, 1),
+    "pulse": (4.0, 0.25, 2.0, 2.0, 2),
+}
+
+
+def timedep_1d(form: str = "cos", n: int = 1024, T: float = 5.0, nsteps: int = 500,
+               scheme: str = "srkn6_4", rule: str = "magnus6", eps_q: float = 0.01) -> Workload:
+    inst = Instance(1, *_grid1(n, -20.0, 20.0),
+                    omega=(TIMEDEP_OMEGA[form], CONST_OMEGA, CONST_OMEGA),
+                    eps=eps_q, vfac=((0.0, 0.0, 0.25, 0.0, 0.0, 0.0), NO_V, NO_V))
+    x = inst.axis(0)
+    psi = _normalise(inst, np.exp(-(x - 1.0) ** 2 / 2.0).astype(np.complex128))
+    return Workload("timedep_1d", [inst], [psi], scheme, rule, T / nsteps, nsteps,
+                    notes="%s trap, N=%d on [-20,20), T=%g" % (form, n, T))
+
+
 CONFIGS = {
     "coherent_1d": coherent_1d,
     "gpe_1d": gpe_1d,
     "batch_1d": batch_1d,
     "gpe_2d": gpe_2d,
     "gpe_3d": gpe_3d,
+    "perturbed_1d": perturbed_1d,
+    "timedep_1d": timedep_1d,
 }
 
 
