@@ -143,6 +143,79 @@ def cpu_baseline(w, K, per_size, gpu_out):
                       "%.1f s" % (len(sample), per_size, K, dt)}, errs
 
 
+# ---------------------------------------------------------------------------
+# The paper's accuracy comparisons, run through the library (complex128):
+#   sec41: Figs. 3-6 -- F-split vs HO-split (Hermite-Fourier) for LF, NI4(8,2),
+#          RKN6_4 and NI5(8,4) at sigma = 0.01, 1, 100 (mu = omega = 1, V_I = 0);
+#   sec42: Figs. 7-8 -- time-dependent traps with a quartic perturbation: F-split
+#          vs HO-split with the CF4, Magnus6 and fundamental-matrix HO rules for
+#          the two fourth-order methods RKN6_4 and NI5(8,4).
+# Error: relative L2 at the final time against a reference run of the same
+# problem with RKN6_4 at 2^14 steps (HO-split; exact_const or fundamental:16).
+# Cost: exponentials per run = FFT pairs = m x steps (the paper's cost axis).
+# ---------------------------------------------------------------------------
+STUDY_SCHEMES = {"sec41": ("leapfrog", "ni4_82", "srkn6_4", "ni5_84"),
+                 "sec42": ("srkn6_4", "ni5_84")}
+
+
+def _study_run(pkg, torch, w, scheme, rule, nsteps):
+    T = w.dt * w.nsteps
+    plan = pkg.Plan(w.instances, scheme, rule, "c128", T / nsteps)
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, w.t0, nsteps)
+    torch.cuda.synchronize()
+    if plan.device_status() != 0:
+        raise RuntimeError("device status")
+    return plan.unpack(buf)[0]
+
+
+def _cost_at(series, target):
+    """FFT pairs needed for rel. error `target` (log-log interpolation), or None."""
+    for (c0, e0), (c1, e1) in zip(series, series[1:]):
+        if e0 >= target > e1 > 0:
+            f = (np.log(target) - np.log(e0)) / (np.log(e1) - np.log(e0))
+            return float(np.exp(np.log(c0) + f * (np.log(c1) - np.log(c0))))
+    return series[0][0] if series and series[0][1] < target else None
+
+
+def study(which):
+    import torch
+    import paper_1007_3470_amd as pkg
+    import workloads as W
+    pkg.load()
+    problems = []
+    if which in ("sec41", "all"):
+        for sig in (0.01, 1.0, 100.0):
+            problems.append(("sec41", "sigma=%g" % sig, W.perturbed_1d(sigma=sig), "exact_const",
+                             ("fsplit", "exact_const")))
+    if which in ("sec42", "all"):
+        for form in ("cos", "pulse"):
+            problems.append(("sec42", form, W.timedep_1d(form=form), "fundamental:16",
+                             ("fsplit", "cf4", "magnus6", "fundamental:8")))
+    steps = [10 * 2 ** k for k in range(11)]
+    for sec, label, w, ref_rule, rules in problems:
+        ref = _study_run(pkg, torch, w, "srkn6_4", ref_rule, 2 ** 14)
+        check = _study_run(pkg, torch, w, "ni5_84", ref_rule, 2 ** 14)
+        out = {"study": sec, "problem": label, "notes": w.notes,
+               "reference": "srkn6_4 + %s, 2^14 steps (ni5_84 at 2^14 differs by %.1e)"
+                            % (ref_rule, W.rel_l2(check, ref)), "curves": {}}
+        for scheme in STUDY_SCHEMES[sec]:
+            m = len(pkg.scheme_preset(scheme)[0])
+            for rule in rules:
+                series = []
+                for n in steps:
+                    try:
+                        u = _study_run(pkg, torch, w, scheme, rule, n)
+                    except pkg.HfgpeError:
+                        continue   # step beyond the rule's validity bound
+                    series.append((m * n, W.rel_l2(u, ref)))
+                out["curves"]["%s/%s" % (scheme, rule)] = {
+                    "fft_pairs_err": [[c, float("%.3e" % e)] for c, e in series],
+                    "cost_1e-4": _cost_at(series, 1e-4), "cost_1e-8": _cost_at(series, 1e-8)}
+        print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,12 +231,18 @@ def main(argv=None):
                     help="only the 2-D and 3-D workloads (for profiling their kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--study", choices=("sec41", "sec42", "all"),
+                    help="run the paper's accuracy-vs-cost comparisons instead of the "
+                         "benchmark (one JSON line per problem)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(instances would be sharded across GPUs with no exchange); use --gpus 1",
               file=sys.stderr)
         return 2
+
+    if args.study:
+        return study(args.study)
 
     import torch
     import paper_1007_3470_amd as pkg
