@@ -28,43 +28,52 @@ __device__ __forceinline__ double2 cmulc(double2 a, double2 b)
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
 // ---------------------------------------------------------------------------
-// exp(-i theta) with a 64-entry table: theta = n pi/32 + r, |r| <= pi/64,
-// exp(-i theta) = T[n mod 64] exp(-i r), T[j] = exp(-i j pi/32) held as a
-// hi + lo pair (tab[j], tab[64 + j]) so the product is rounded once and
-// carries no magnitude bias; short Taylor series for r (sin through r^9, cos
-// through r^10: truncation < 1e-20).  Roughly 60% of cis_neg's operations.
+// exp(-i theta) with a 256-entry table: theta = n pi/128 + r, |r| <= pi/256,
+// exp(-i theta) = T_n exp(-i r) with T_n = exp(-i n pi/128) (n mod 256).
+// The table holds T_n rounded to FP64, t, together with its rounding error
+// written as a relative correction: T_n = t (1 + a + i b), |a|, |b| ~ 1e-16
+// (kept as floats).  Up to O(1e-32), T_n exp(-i r) = t (1 + a) exp(-i (r - b)),
+// so the angle error enters the series argument and the magnitude error the
+// cosine term; the product with t is then rounded once and the table adds no
+// magnitude bias.  Series: sin through rho^7, cos - 1 through rho^6
+// (truncation < 2e-20 on |rho| <= pi/256).
 // ---------------------------------------------------------------------------
-constexpr int kCisTable = 64;
+constexpr int kCisTable = 256;
 
-__device__ __forceinline__ double2 cis_neg_tab(double theta, const double2 *__restrict__ tab)
+struct CisTable {
+    double2 t[kCisTable];  // exp(-i n pi/128) rounded to FP64
+    float2 c[kCisTable];   // (b, a): angle and magnitude parts of the rounding error
+};
+
+__device__ __forceinline__ double2 cis_neg_tab(double theta, const CisTable &tab)
 {
-    const double K32 = 10.185916357881302;        // 32 / pi
-    const double C_HI = 0.09817477042468103;      // pi/32 (leading word)
-    const double C_LO = 3.827021247335479e-18;    // pi/32 - C_HI
-    double n = rint(theta * K32);
+    const double K = 40.743665431525208;          // 128 / pi
+    const double C_HI = 0.024543692606170259;     // pi/128 (leading word)
+    const double C_LO = 9.5714723039735938e-19;   // pi/128 - C_HI
+    double n = rint(theta * K);
     double r = fma(-n, C_HI, theta);
     r = fma(-n, C_LO, r);
-    double r2 = r * r;
-    double ps = fma(r2, 2.7557319223985893e-06, -1.984126984126984e-04);  // 1/9!, -1/7!
-    ps = fma(ps, r2, 8.333333333333333e-03);                               // 1/5!
-    ps = fma(ps, r2, -1.6666666666666666e-01);                             // -1/3!
-    double s = fma(r * r2, ps, r);
-    double pc = fma(r2, 2.755731922398589e-07, -2.48015873015873e-05);    // 1/10!, -1/8!
-    pc = fma(pc, r2, 1.3888888888888889e-03);                              // 1/6!
-    pc = fma(pc, r2, -4.1666666666666664e-02);                             // -1/4!
-    double hr = 0.5 * r2;
-    double w = 1.0 - hr;
-    double c = w + (((1.0 - w) - hr) - r2 * r2 * pc);
     const int j = ((int)n) & (kCisTable - 1);
-    const double2 th = tab[j], tl = tab[kCisTable + j];
-    // (th + tl) (c - i s)
-    return make_double2(fma(th.x, c, fma(th.y, s, fma(tl.x, c, tl.y * s))),
-                        fma(th.y, c, fma(-th.x, s, fma(tl.y, c, -tl.x * s))));
+    const float2 cor = tab.c[j];
+    const double2 t = tab.t[j];
+    const double rho = r - (double)cor.x;
+    const double r2 = rho * rho;
+    double ps = fma(r2, -1.984126984126984e-04, 8.333333333333333e-03);  // -1/7!, 1/5!
+    ps = fma(ps, r2, -1.6666666666666666e-01);                           // -1/3!
+    const double sn = fma(rho * r2, ps, rho);
+    double pc = fma(r2, -1.3888888888888889e-03, 4.1666666666666664e-02);  // -1/6!, 1/4!
+    pc = fma(pc, r2, -0.5);
+    const double cm = fma(r2, pc, (double)cor.y);  // cos(rho) - 1 + a
+    // t (1 + cm - i sn)
+    return make_double2(fma(t.x, cm, fma(t.y, sn, t.x)), fma(t.y, cm, fma(-t.x, sn, t.y)));
 }
 
-__device__ __forceinline__ void load_cis_table(double2 *lds_tab, const double2 *__restrict__ gtab)
+// copy the table (as raw 16-byte words) from global memory into LDS
+__device__ __forceinline__ void load_cis_table(CisTable *lds_tab, const double2 *__restrict__ gtab)
 {
-    for (int j = threadIdx.x; j < 2 * kCisTable; j += blockDim.x) lds_tab[j] = gtab[j];
+    double2 *dst = reinterpret_cast<double2 *>(lds_tab);
+    constexpr int kWords = (int)(sizeof(CisTable) / sizeof(double2));
+    for (int j = threadIdx.x; j < kWords; j += blockDim.x) dst[j] = gtab[j];
 }
 
 // ---------------------------------------------------------------------------

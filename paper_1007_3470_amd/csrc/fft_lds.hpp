@@ -172,4 +172,93 @@ struct Fft1D {
     }
 };
 
+// Fixed-shape radix-8 FFT of the resident 1-D kernel: N = 2^LOGN points split
+// over T = N/8 threads (T a multiple of 8), FP64 exchange, one padding element
+// every 8 (as Fft1D with pad = true, istride = 1).  With the shape known at
+// compile time each LDS address is a per-thread base plus a constant, so the
+// addresses of all passes fold into instruction offsets instead of occupying
+// registers across the step loop.  The padding algebra used below:
+// pad(x + y) = pad(x) + y + (y >> 3) whenever (x mod 8) + (y mod 8) < 8.
+template <int LOGN>
+struct FftFix8 {
+    static constexpr int P = 8, LOGP = 3;
+    static constexpr int N = 1 << LOGN;
+    static constexpr int LOGT = LOGN - LOGP;
+    static constexpr int T = 1 << LOGT;
+    static constexpr int S = (LOGN + LOGP - 1) / LOGP;  // passes
+    static constexpr int R0LOG = LOGN - LOGP * (S - 1);  // pass 0 has radix 2^R0LOG
+    static constexpr int R0 = 1 << R0LOG;
+    static constexpr int ROW = N + (N >> kPadShift);     // padded elements per instance
+    static constexpr int TP = T + (T >> 3);              // padded stride of the points {t + cT}
+    static_assert(kPadShift == 3 && T % 8 == 0 && S >= 2, "fixed-shape FFT: N >= 64");
+
+    double2 *lds;
+    int roff;             // pad(t) + instance row
+    int w0off;            // pad(t R0) + instance row
+    int woff[S > 2 ? S - 2 : 1];  // pass s write base, s = 1 .. S-2
+    double2 tw[S - 1][3];         // w^1, w^2, w^4 of passes 1 .. S-1
+
+    __device__ __forceinline__ void init(int tl, int slot, double2 *lds_)
+    {
+        lds = lds_;
+        const int row = slot * ROW;
+        roff = row + tl + (tl >> 3);
+        const int x0 = tl * R0;
+        w0off = row + x0 + (x0 >> 3);
+        constexpr double invN = 1.0 / (double)N;
+#pragma unroll
+        for (int s = 1; s < S; ++s) {
+            const int logL = R0LOG + LOGP * (s - 1);
+            const int k = tl & ((1 << logL) - 1);
+            if (s < S - 1) {
+                const int base = (tl - k) * P + k;
+                woff[s - 1] = row + base + (base >> 3);
+            }
+            const int slog = LOGN - logL - LOGP;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int e = ((1 << q) * k) << slog;
+                double sn, cs;
+                sincospi(-2.0 * (double)e * invN, &sn, &cs);
+                tw[s - 1][q] = make_double2(cs, sn);
+            }
+        }
+    }
+
+    template <int SGN>
+    __device__ __forceinline__ void run(double2 *u)
+    {
+        // pass 0: radix R0 on the thread's own points {t + cT}
+        constexpr int NB = P / R0;
+        constexpr int BSTR = T * R0 + ((T * R0) >> 3);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double2 v[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[r] = u[b + r * NB];
+            Dft<R0, SGN>::run(v);
+#pragma unroll
+            for (int rp = 0; rp < R0; ++rp) lds[w0off + b * BSTR + rp] = v[rp];
+        }
+#pragma unroll
+        for (int s = 1; s < S; ++s) {
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < P; ++c) u[c] = lds[roff + c * TP];
+            __syncthreads();
+            const double2 w1 = tw[s - 1][0], w2 = tw[s - 1][1], w4 = tw[s - 1][2];
+            const double2 w3 = cmul(w1, w2);
+            const double2 w[7] = {w1, w2, w3, w4, cmul(w1, w4), cmul(w2, w4), cmul(w3, w4)};
+#pragma unroll
+            for (int r = 1; r < P; ++r) u[r] = (SGN < 0) ? cmul(u[r], w[r - 1]) : cmulc(u[r], w[r - 1]);
+            Dft<P, SGN>::run(u);
+            if (s < S - 1) {
+                const int L = 1 << (R0LOG + LOGP * (s - 1));
+#pragma unroll
+                for (int rp = 0; rp < P; ++rp) lds[woff[s - 1] + rp * L + ((rp * L) >> 3)] = u[rp];
+            }
+        }
+    }
+};
+
 }  // namespace hfgpe

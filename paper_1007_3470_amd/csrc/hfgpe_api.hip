@@ -46,6 +46,7 @@ int ilog2(int n)
 
 struct Group1D {
     int P = 0;
+    bool fixed = false;  // every item in 64 <= N <= 2048: the fixed-shape kernel
     int logn = -1;  // >= 0 when the group holds a single grid size (plain mode)
     std::vector<Item1D> items;
     Item1D *d_items = nullptr;
@@ -77,7 +78,7 @@ struct hfgpe_plan {
     double *d_part = nullptr;
     double *d_kin = nullptr;
     int nblk = 1;
-    double2 *d_cistab = nullptr;  // exp(-i j pi/32), j < 64, hi then lo words
+    double2 *d_cistab = nullptr;  // phase table (CisTable), exp(-i n pi/128) and corrections
     double2 *d_twtab = nullptr;   // d-D: exp(-2 pi i q / 2^twlog)
     // d-D graph replay: a block of kGraphSteps steps captured once per record
     // row stride; the pass kernels add *d_graph_base to their step offsets
@@ -298,11 +299,12 @@ void build_groups_1d(hfgpe_plan &P, bool plain)
         while (j < P.n_inst && P.insts[order[j]].n[0] == n) ++j;
         Group1D *grp = nullptr;
         for (auto &g : P.groups)
-            if (g.P == Pp && (!plain || g.logn == ilog2(n))) grp = &g;
+            if (g.P == Pp && g.fixed == fixed_shape_1d(n) && (!plain || g.logn == ilog2(n))) grp = &g;
         if (!grp) {
             P.groups.emplace_back();
             grp = &P.groups.back();
             grp->P = Pp;
+            grp->fixed = fixed_shape_1d(n);
             grp->logn = plain ? ilog2(n) : -1;
         }
         for (int k = i; k < j; k += G) {
@@ -619,19 +621,23 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
     ALLOC_TRY(P->d_part, sizeof(double) * 4 * (size_t)n_inst * P->nblk);
     ALLOC_TRY(P->d_kin, sizeof(double) * n_inst);
     {
-        // phase-factor table: exp(-i j pi/32) split into hi + lo words, evaluated
-        // in extended precision on the host
-        std::vector<double2> tab(2 * kCisTable);
+        // phase-factor table: t_n = exp(-i n pi/128) rounded to FP64, and its
+        // rounding error as the relative correction (a, b) with
+        // exp(-i n pi/128) = t_n (1 + a + i b); evaluated in extended precision
+        CisTable tab;
         const long double pi = 3.14159265358979323846264338327950288L;
         for (int j = 0; j < kCisTable; ++j) {
-            long double a = (long double)j * pi / 32.0L;
-            long double c = cosl(a), s = -sinl(a);
-            double ch = (double)c, sh = (double)s;
-            tab[j] = make_double2(ch, sh);
-            tab[kCisTable + j] = make_double2((double)(c - (long double)ch), (double)(s - (long double)sh));
+            long double ang = (long double)j * pi / 128.0L;
+            long double cx = cosl(ang), cy = -sinl(ang);
+            double hx = (double)cx, hy = (double)cy;
+            long double dx = cx - hx, dy = cy - hy;
+            long double n2 = (long double)hx * hx + (long double)hy * hy;
+            long double a = (dx * hx + dy * hy) / n2, b = (dy * hx - dx * hy) / n2;
+            tab.t[j] = make_double2(hx, hy);
+            tab.c[j] = make_float2((float)b, (float)a);
         }
-        ALLOC_TRY(P->d_cistab, sizeof(double2) * tab.size());
-        COPY_TRY(P->d_cistab, tab.data(), sizeof(double2) * tab.size());
+        ALLOC_TRY(P->d_cistab, sizeof(CisTable));
+        COPY_TRY(P->d_cistab, &tab, sizeof(CisTable));
     }
     for (auto &g : P->groups) {
         ALLOC_TRY(g.d_items, sizeof(Item1D) * g.items.size());
@@ -759,6 +765,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
                 L.items = g.d_items;
                 L.n_items = (int)g.items.size();
                 L.P = g.P;
+                L.fixed = g.fixed ? 1 : 0;
                 L.perm = P->d_perm;
                 L.insts = P->d_insts;
                 L.rec = P->d_rec;

@@ -49,9 +49,9 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     constexpr int LOGP = Log2<P>::value;
     constexpr int LDS_ELEMS = TPB * P + ((TPB * P) >> kPadShift);
     __shared__ double2 lds[LDS_ELEMS];
-    __shared__ double2 ctab[2 * kCisTable];
+    __shared__ CisTable ctab;
     __shared__ double2 kfl[kMaxAxisND];  // drift factor of every wavenumber of the axis
-    load_cis_table(ctab, cistab);
+    load_cis_table(&ctab, cistab);
     __syncthreads();
 
     const int lnj = sh.logn[axis];

@@ -27,12 +27,13 @@ hipError_t launch_coeff(const LaunchCoeff &L);
 struct Launch1D {
     const Item1D *items;
     int n_items;
-    int P;  // points per thread of this item group
+    int P;      // points per thread of this item group
+    int fixed;  // 1: every item has 64 <= N <= 2048 (fixed-shape kernel)
     const int *perm;
     const InstDev *insts;
     const Rec *rec;
     const Rec *rec_open;
-    const double2 *cistab;  // 2 x 64 entries: exp(-i j pi/32) as hi, lo
+    const double2 *cistab;  // the phase table (CisTable layout), 16-byte words
     void *psi;
     int m;
     int K;            // steps advanced by this launch
@@ -44,6 +45,7 @@ struct Launch1D {
 };
 hipError_t launch_hf1d(const Launch1D &L);
 int points_per_thread_1d(int n);
+bool fixed_shape_1d(int n);
 
 // ---- observables (kern_reduce.hip) ----------------------------------------
 // Per-instance partial sums written to part[(inst * nblk + blk) * 4 + q] as
