@@ -148,13 +148,14 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
 
     auto xphase = [&](const Rec &r) {
         const double chi = r.chi[0], w = r.w, s = r.s;
+        double th[P];
 #pragma unroll
         for (int c = 0; c < P; ++c) {
             const double x = lo + (double)(tl + c * T) * dx;
             const double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
-            const double th = fma(chi, 0.5 * x * x, fma(w, ve[c * T], s * a2));
-            u[c] = cmul(u[c], cis_neg_tab(th, ctab));
+            th[c] = fma(chi, 0.5 * x * x, fma(w, ve[c * T], s * a2));
         }
+        cis_apply_batch<P>(u, th, ctab);
     };
 
     constexpr double invN = 1.0 / (double)N;
@@ -166,14 +167,15 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
             const Rec r = rp[step * m + st];
             fft.template run<-1>(u);
             const double g = r.g[0];
+            double th[P];
 #pragma unroll
             for (int c = 0; c < P; ++c) {
                 // wavenumber index: the upper half of the points is negative
                 const int sq = tl + c * T - ((c >= P / 2) ? N : 0);
                 const double k = ks * (double)sq;
-                const double2 f = cis_neg_tab(g * (0.5 * k * k), ctab);
-                u[c] = cmul(u[c], make_double2(f.x * invN, f.y * invN));
+                th[c] = g * (0.5 * k * k);
             }
+            cis_apply_batch<P>(u, th, ctab, invN);
             fft.template run<+1>(u);
             xphase(r);
         }
