@@ -51,6 +51,10 @@ def flops_per_gp_step(n: int, m: int) -> float:
     return m * (10.0 * np.log2(n) + 19.0)
 
 
+def progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def timed_evolve(pkg, torch, w, dtype, K, warmup, **kw):
     plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, profile=True, **kw)
     if warmup > 0:
@@ -74,6 +78,7 @@ def timed_evolve(pkg, torch, w, dtype, K, warmup, **kw):
     status = plan.device_status()
     if status != 0:
         raise RuntimeError("device status %d" % status)
+    progress("%s %s%s: %d steps in %.3f s" % (w.name, dtype, " plain" if kw.get("plain") else "", K, wall))
     return plan, buf, wall, gpu_ms, step_ms, coeff_ms, launches
 
 
@@ -106,6 +111,7 @@ def nd_workload(pkg, torch, W, w, sc_bytes):
         out[dtype] = {"value": w.points * w.nsteps / wall, "ms_per_step": wall * 1e3 / w.nsteps,
                       "pass_us": pass_s * 1e6, "pass_GBs": bw, "pass_frac_of_hbm_peak": bw / HBM_PEAK_GBS}
     out["l2_c64_vs_c128_max"] = max(W.rel_l2(a, b) for a, b in zip(res["c64"], res["c128"]))
+    progress("%s done" % w.name)
     out["workload"] = w.notes + ", %s + %s, dt=%g, %d steps" % (w.scheme, w.ho_rule, w.dt, w.nsteps)
     return out
 
@@ -136,6 +142,7 @@ def cpu_baseline(w, K, per_size, gpu_out):
     refs = {k: oracle.evolve(w.instances[k], w.psi0[k], w.scheme, w.ho_rule, w.dt, 0.0, K)
             for k in sample}
     dt = time.perf_counter() - t0
+    progress("cpu baseline: %d instances in %.1f s" % (len(sample), dt))
     pts = sum(w.instances[k].n[0] for k in sample)
     errs = {name: max(W.rel_l2(out[k], refs[k]) for k in sample) for name, out in gpu_out.items()}
     return {"value": pts * K / dt, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
@@ -287,7 +294,7 @@ def main(argv=None):
     traffic = load_traffic(kernel_source_hash())
     roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-            "kernel": "hf1d_kernel<float2> (resident 1-D step)",
+            "kernel": "hf1d_fixed_kernel<float2> (resident 1-D step, 64 <= N <= 2048)",
             "avg_launch_ms": avg_launch_s * 1e3, "launches": nl64,
             "flops_per_gp_step": "10 log2 N + 19 per stage"}
 
