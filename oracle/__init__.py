@@ -19,6 +19,10 @@ Parity status per function (the pins live in ``tests/test_oracle_*.py``):
                   of the same 2x2 system, its sub-step order, and its
                   reductions (one sub-step = Magnus6; constant omega = exact)
   stage_coeffs    pinned: K(f) D(g) K(e) product reproduces the stage matrix
+  coupled trap    pinned: stage matrix vs scipy expm / DOP853; symplectic, F and E
+                  symmetric, K(F) D(G) K(E) reproduces S; rotated-trap coherent
+                  state and ground state closed forms; d-D Gaussian-packet
+                  (matrix Riccati) reference for the time-dependent order
   evolve          pinned: coherent-state closed form (linear, constant omega),
                   ground-state single step (Fig. 1 experiment), norm
                   conservation, time reversibility, observed order under
@@ -41,7 +45,7 @@ _SRC = os.path.join(_HERE, "hfgpe_oracle.c")
 _SO = os.path.join(_HERE, "libhfgpe_oracle.so")
 _LIB = None
 
-NPAR = 40
+NPAR = 43
 HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2, "fsplit": 3, "fundamental": 4}
 FUNDAMENTAL_DEFAULT_SUBSTEPS = 16
 _ERRORS = {-1: "invalid argument", -2: "singular stage (g = 0)",
@@ -74,6 +78,10 @@ def _lib():
                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_long, dp]
         lib.orc_drift.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp]
+        lib.orc_stage_matrix_full.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double,
+                                              ctypes.c_double, dp]
+        lib.orc_stage_coeffs_full.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int,
+                                              ctypes.c_double, ctypes.c_double, dp, ip]
         lib.orc_norm.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp]
         lib.orc_energy.argtypes = [ctypes.c_int, ip, dp, dp, dp, ctypes.c_double, dp, dp]
         assert lib.orc_npar() == NPAR
@@ -147,6 +155,7 @@ def params_block(inst) -> np.ndarray:
     p[13:17] = inst.sigma[:4]
     p[39] = inst.sigma[4] if len(inst.sigma) > 4 else 0
     p[17] = inst.eps
+    p[40:43] = getattr(inst, "wcross", (0.0, 0.0, 0.0))
     return p
 
 
@@ -176,6 +185,30 @@ def stage_matrix(inst, rule: str, axis: int, t0: float, tau: float) -> np.ndarra
     _check(_lib().orc_stage_matrix(*rule_id(rule), _dp(params_block(inst)), axis, t0, tau,
                                    _dp(S)))
     return S.reshape(2, 2)
+
+
+def stage_matrix_full(inst, rule: str, t0: float, tau: float) -> np.ndarray:
+    """2d x 2d stage matrix S of a coupled trap (non-diagonal W), acting on (x, p)."""
+    d = inst.ndim
+    S = np.zeros(4 * d * d)
+    _check(_lib().orc_stage_matrix_full(HO_RULES[rule], _dp(params_block(inst)), d, t0, tau,
+                                        _dp(S)))
+    return S.reshape(2 * d, 2 * d)
+
+
+def stage_coeffs_full(inst, scheme: str, rule: str, dt: float, tn: float) -> np.ndarray:
+    """F, G, E (d x d each) of every factor triple of a coupled-trap step, in
+    the order they act (one per stage for exact_const, two for cf4):
+    shape (triples, 3, d, d)."""
+    a, _ = scheme_coefficients(scheme)
+    a = np.array(a)
+    d = inst.ndim
+    out = np.zeros(2 * len(a) * 3 * d * d)
+    nout = np.zeros(1, dtype=np.int32)
+    _check(_lib().orc_stage_coeffs_full(d, _dp(params_block(inst)), len(a), _dp(a),
+                                        HO_RULES[rule], dt, tn, _dp(out), _ip(nout)))
+    k = int(nout[0])
+    return out[: k * 3 * d * d].reshape(k, 3, d, d)
 
 
 def stage_coeffs(inst, scheme: str, rule: str, dt: float, tn: float) -> np.ndarray:

@@ -29,6 +29,11 @@
  *     the B flow (Lemma 1, frozen time) and the A flow = K(f) D(g) K(e),
  *     applied one after the other WITHOUT merging adjacent x-phases (the
  *     GPU library merges them; the unmerged order is the cross-check);
+ *   - a coupled trap (non-diagonal W, Sec. 1's general x^T M x): the stage
+ *     flow is a 2d x 2d symplectic matrix, built per normal mode of the
+ *     (averaged) W and factored as K(F) D(G) K(E) with symmetric d x d
+ *     matrices, G = S12, E = G^-1 (I - S11), F = (I - S22) G^-1; chirps and
+ *     drift are then full quadratic forms x^T C x / 2 and k^T G k / 2;
  *   - norm and energy observables (Sec. 1).
  *
  * Conventions (readings where the paper is silent):
@@ -46,6 +51,10 @@
  *   [18+6j..23+6j] V_I factor of axis j: c0, c2, c4, gs, k, phi
  *                  v_j(x) = (c0 + c2 x^2 + c4 x^4) * (gs > 0 ? exp(-x^2/gs) : 1)
  *                           * cos(k x + phi);   V_I = prod_j v_j(x_j)
+ *   [40..42]       W_xy, W_xz, W_yz: constant off-diagonal entries of the
+ *                  squared-frequency matrix W(t) of a coupled trap
+ *                  V_HO = (mu/2) x^T W(t) x, W_jj = omega_j(t)^2 (the general
+ *                  quadratic potential x^T M x of Sec. 1 with M = mu W / 2)
  *   [36+j], [39]   form of omega_j(t), sigma(t):
  *                  0: v(t)   = v0 (1 + amp sin(freq t + phase))
  *                  1: v(t)^2 = v0 (1 + amp sin(freq t + phase))  (the modulated
@@ -59,7 +68,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_NPAR 40
+#define ORC_NPAR 43
 #define ORC_PI 3.14159265358979323846
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ESINGULAR = -2, ORC_EFREQ = -3, ORC_ENOMEM = -4 };
@@ -97,6 +106,28 @@ static double par_sigma(const double *p, double t)
 }
 
 static double par_eps(const double *p) { return p[17]; }
+
+/* Off-diagonal W_ij of the coupled trap (i != j, axes < 3). */
+static double par_wcross(const double *p, int i, int j)
+{
+    if (i > j) { int t = i; i = j; j = t; }
+    if (i == 0 && j == 1) return p[40];
+    if (i == 0 && j == 2) return p[41];
+    return p[42];
+}
+
+static int par_coupled(const double *p, int ndim)
+{
+    return ndim >= 2 && (p[40] != 0.0 || (ndim == 3 && (p[41] != 0.0 || p[42] != 0.0)));
+}
+
+/* W(t), d x d, row-major. */
+static void par_wmat(const double *p, int d, double t, double *W)
+{
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            W[i * d + j] = (i == j) ? par_omega_sq(p, i, t) : par_wcross(p, i, j);
+}
 
 /* One separable factor of the perturbing potential V_I. */
 static double vfactor(const double *p, int j, double x)
@@ -399,6 +430,270 @@ int orc_stage_coeffs(int ndim, const double *par, int m, const double *a, int ru
 }
 
 /* ------------------------------------------------------------------------ */
+/* Coupled trap: 2d x 2d stage matrices (d <= 3)                            */
+/* ------------------------------------------------------------------------ */
+
+/* Symmetric eigen-decomposition W = Q diag(lam) Q^T by cyclic Jacobi
+ * rotations (d <= 3); Q holds the eigenvectors as columns. */
+static void sym_eig(int d, const double *Win, double *lam, double *Q)
+{
+    double A[9];
+    memcpy(A, Win, sizeof(double) * d * d);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) Q[i * d + j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = i + 1; j < d; ++j) off += A[i * d + j] * A[i * d + j];
+        if (off < 1e-300) break;
+        for (int pq = 0; pq < d; ++pq)
+            for (int qq = pq + 1; qq < d; ++qq) {
+                double apq = A[pq * d + qq];
+                if (apq == 0.0) continue;
+                double theta = (A[qq * d + qq] - A[pq * d + pq]) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < d; ++k) { /* A <- J^T A J */
+                    double akp = A[k * d + pq], akq = A[k * d + qq];
+                    A[k * d + pq] = c * akp - sn * akq;
+                    A[k * d + qq] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < d; ++k) {
+                    double apk = A[pq * d + k], aqk = A[qq * d + k];
+                    A[pq * d + k] = c * apk - sn * aqk;
+                    A[qq * d + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < d; ++k) {
+                    double qkp = Q[k * d + pq], qkq = Q[k * d + qq];
+                    Q[k * d + pq] = c * qkp - sn * qkq;
+                    Q[k * d + qq] = sn * qkp + c * qkq;
+                }
+            }
+    }
+    for (int i = 0; i < d; ++i) lam[i] = A[i * d + i];
+}
+
+static void mat_mul(int d, const double *A, const double *B, double *C)
+{
+    double T[9];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < d; ++k) acc += A[i * d + k] * B[k * d + j];
+            T[i * d + j] = acc;
+        }
+    memcpy(C, T, sizeof(double) * d * d);
+}
+
+/* Inverse by Gauss-Jordan elimination with partial pivoting. */
+static int mat_inv(int d, const double *Ain, double *X)
+{
+    double A[9];
+    memcpy(A, Ain, sizeof(double) * d * d);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) X[i * d + j] = (i == j) ? 1.0 : 0.0;
+    for (int c = 0; c < d; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < d; ++r)
+            if (fabs(A[r * d + c]) > fabs(A[piv * d + c])) piv = r;
+        if (!(fabs(A[piv * d + c]) > 1e-300)) return ORC_ESINGULAR;
+        for (int k = 0; k < d; ++k) {
+            double t = A[c * d + k]; A[c * d + k] = A[piv * d + k]; A[piv * d + k] = t;
+            t = X[c * d + k]; X[c * d + k] = X[piv * d + k]; X[piv * d + k] = t;
+        }
+        double inv = 1.0 / A[c * d + c];
+        for (int k = 0; k < d; ++k) { A[c * d + k] *= inv; X[c * d + k] *= inv; }
+        for (int r = 0; r < d; ++r) {
+            if (r == c) continue;
+            double f = A[r * d + c];
+            for (int k = 0; k < d; ++k) { A[r * d + k] -= f * A[c * d + k]; X[r * d + k] -= f * X[c * d + k]; }
+        }
+    }
+    return ORC_OK;
+}
+
+/* A 2d x 2d matrix in deviation form, as four d x d blocks: S = I + X. */
+typedef struct { double b[4][9]; } blk_t;
+
+/* Flow over tau of H = p^2/(2 mu) + (mu/2) x^T W x, W constant and positive
+ * definite: per normal mode (W = Q diag(w_k^2) Q^T) the constant-frequency
+ * flow of Lemma 2's proof, rotated back.  Deviation form. */
+static int ho_flow_full(int d, const double *W, double mu, double tau, blk_t *X)
+{
+    double lam[3], Q[9];
+    sym_eig(d, W, lam, Q);
+    double cm[3], s1[3], s2[3];
+    for (int k = 0; k < d; ++k) {
+        if (!(lam[k] > 0.0)) return ORC_EFREQ;
+        double w = sqrt(lam[k]);
+        cm[k] = cosm1(w * tau);
+        s1[k] = sin(w * tau) / (mu * w);
+        s2[k] = -mu * w * sin(w * tau);
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double a = 0, b = 0, c = 0;
+            for (int k = 0; k < d; ++k) {
+                double qq = Q[i * d + k] * Q[j * d + k];
+                a += qq * cm[k];
+                b += qq * s1[k];
+                c += qq * s2[k];
+            }
+            X->b[0][i * d + j] = a;
+            X->b[1][i * d + j] = b;
+            X->b[2][i * d + j] = c;
+            X->b[3][i * d + j] = a;
+        }
+    return ORC_OK;
+}
+
+/* (I + A)(I + B) = I + A + B + A B, blockwise. */
+static void blk_mul(int d, const blk_t *A, const blk_t *B, blk_t *C)
+{
+    blk_t T;
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+            double P1[9], P2[9];
+            mat_mul(d, A->b[r * 2 + 0], B->b[0 * 2 + c], P1);
+            mat_mul(d, A->b[r * 2 + 1], B->b[1 * 2 + c], P2);
+            for (int k = 0; k < d * d; ++k)
+                T.b[r * 2 + c][k] = A->b[r * 2 + c][k] + B->b[r * 2 + c][k] + (P1[k] + P2[k]);
+        }
+    *C = T;
+}
+
+/* Stage matrix of the coupled trap over [t0, t0 + tau]: the exact flow for a
+ * constant W (rule exact_const), or the commutator-free product of
+ * Eq. CommutatorFree with W averaged at the two Gauss nodes (rule cf4; the
+ * factor weighted to the earlier node acts first). */
+static int ho_stage_full(int rule, const double *p, int d, double t0, double tau, blk_t *X)
+{
+    double mu = par_mu(p);
+    if (rule == ORC_HO_EXACT_CONST) {
+        double W[9];
+        par_wmat(p, d, t0, W);
+        return ho_flow_full(d, W, mu, tau, X);
+    }
+    if (rule == ORC_HO_CF4) {
+        double c1 = 0.5 - sqrt(3.0) / 6.0, c2 = 0.5 + sqrt(3.0) / 6.0;
+        double al = 0.5 - 1.0 / sqrt(3.0), be = 1.0 - al;
+        double W1[9], W2[9], WL[9], WR[9];
+        par_wmat(p, d, t0 + c1 * tau, W1);
+        par_wmat(p, d, t0 + c2 * tau, W2);
+        for (int k = 0; k < d * d; ++k) {
+            WL[k] = al * W1[k] + be * W2[k];
+            WR[k] = be * W1[k] + al * W2[k];
+        }
+        blk_t L, R;
+        int rc = ho_flow_full(d, WL, mu, 0.5 * tau, &L);
+        if (rc) return rc;
+        rc = ho_flow_full(d, WR, mu, 0.5 * tau, &R);
+        if (rc) return rc;
+        blk_mul(d, &L, &R, X);
+        return ORC_OK;
+    }
+    return ORC_EINVAL;  /* other rules are written for a diagonal W */
+}
+
+/* S = I + X = K(F) D(G) K(E) with K(C) = [[I, 0], [-C, I]], D(G) = [[I, G], [0, I]]:
+ * G = S12, E = -G^-1 X11, F = -X22 G^-1. */
+static int factor_kdk_full(int d, const blk_t *X, double *F, double *Gm, double *E)
+{
+    double Gi[9] = {0};
+    memcpy(Gm, X->b[1], sizeof(double) * d * d);
+    int rc = mat_inv(d, Gm, Gi);
+    if (rc) return rc;
+    mat_mul(d, Gi, X->b[0], E);
+    mat_mul(d, X->b[3], Gi, F);
+    for (int k = 0; k < d * d; ++k) { E[k] = -E[k]; F[k] = -F[k]; }
+    return ORC_OK;
+}
+
+/* The K(F) D(G) K(E) factors (symmetric d x d) that make up one stage of the
+ * coupled trap, in the order they act.  For d >= 2 the triple K(F) D(G) K(E)
+ * spans only flows whose S12 block is symmetric; the flow of a constant W is
+ * one of them (per normal mode it is Lemma 2), but the commutator-free
+ * product of two different W is in general not.  So the exact rule gives one
+ * factor triple, and the commutator-free rule gives its two exponentials as
+ * two triples: the flow of W_R over tau/2, then that of W_L over tau/2. */
+static int coupled_factors(int rule, const double *p, int d, double t0, double tau, double *F,
+                           double *Gm, double *E, int *nf)
+{
+    double mu = par_mu(p);
+    blk_t X;
+    if (rule == ORC_HO_EXACT_CONST) {
+        double W[9];
+        par_wmat(p, d, t0, W);
+        int rc = ho_flow_full(d, W, mu, tau, &X);
+        if (rc) return rc;
+        *nf = 1;
+        return factor_kdk_full(d, &X, F, Gm, E);
+    }
+    if (rule == ORC_HO_CF4) {
+        double c1 = 0.5 - sqrt(3.0) / 6.0, c2 = 0.5 + sqrt(3.0) / 6.0;
+        double al = 0.5 - 1.0 / sqrt(3.0), be = 1.0 - al;
+        double W1[9], W2[9], WL[9], WR[9];
+        par_wmat(p, d, t0 + c1 * tau, W1);
+        par_wmat(p, d, t0 + c2 * tau, W2);
+        for (int k = 0; k < d * d; ++k) {
+            WL[k] = al * W1[k] + be * W2[k];
+            WR[k] = be * W1[k] + al * W2[k];
+        }
+        const double *Ws[2] = {WR, WL};
+        for (int h = 0; h < 2; ++h) {
+            int rc = ho_flow_full(d, Ws[h], mu, 0.5 * tau, &X);
+            if (rc) return rc;
+            rc = factor_kdk_full(d, &X, F + 9 * h, Gm + 9 * h, E + 9 * h);
+            if (rc) return rc;
+        }
+        *nf = 2;
+        return ORC_OK;
+    }
+    return ORC_EINVAL;
+}
+
+/* Public (tests): the 2d x 2d stage matrix S of the coupled trap, row-major. */
+int orc_stage_matrix_full(int rule, const double *par, int d, double t0, double tau, double *S)
+{
+    blk_t X;
+    if (d < 2 || d > 3) return ORC_EINVAL;
+    int rc = ho_stage_full(rule, par, d, t0, tau, &X);
+    if (rc) return rc;
+    int n = 2 * d;
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) {
+            int br = r / d, bc = c / d;
+            S[r * n + c] = X.b[br * 2 + bc][(r % d) * d + (c % d)] + (r == c ? 1.0 : 0.0);
+        }
+    return ORC_OK;
+}
+
+/* Public (tests): F, G, E (each d x d, row-major) of every factor triple of
+ * the step starting at tn for the coupled trap, in the order they act (one
+ * per stage for exact_const, two per stage for cf4):
+ * out[(f*3 + {0,1,2}) * d*d + ...]; *nout = number of triples. */
+int orc_stage_coeffs_full(int d, const double *par, int m, const double *a, int rule, double dt,
+                          double tn, double *out, int *nout)
+{
+    double tau = tn;
+    int k = 0;
+    for (int i = 0; i < m; ++i) {
+        double F[18], Gm[18], E[18];
+        int nf = 0;
+        int rc = coupled_factors(rule, par, d, tau, a[i] * dt, F, Gm, E, &nf);
+        if (rc) return rc;
+        for (int h = 0; h < nf; ++h, ++k) {
+            memcpy(out + (k * 3 + 0) * d * d, F + 9 * h, sizeof(double) * d * d);
+            memcpy(out + (k * 3 + 1) * d * d, Gm + 9 * h, sizeof(double) * d * d);
+            memcpy(out + (k * 3 + 2) * d * d, E + 9 * h, sizeof(double) * d * d);
+        }
+        tau = tau + a[i] * dt;
+    }
+    *nout = k;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Pointwise flows and the time step                                         */
 /* ------------------------------------------------------------------------ */
 
@@ -527,6 +822,51 @@ static int apply_D(const grid_t *G, double *u, const double *g)
     return orc_fftn(G->ndim, G->n, u, +1);
 }
 
+/* Coordinates (or wavenumbers) of grid point idx along every axis. */
+static void point_coords(const grid_t *G, long idx, double *x, double *k)
+{
+    for (int j = 0; j < G->ndim; ++j) {
+        long i = axis_index(G, idx, j);
+        if (x) x[j] = G->lo[j] + i * G->dx[j];
+        if (k) {
+            double L = G->dx[j] * G->n[j];
+            long q = (i < G->n[j] / 2) ? i : i - G->n[j];
+            k[j] = 2.0 * ORC_PI / L * (double)q;
+        }
+    }
+}
+
+static double quad_form(int d, const double *C, const double *v)
+{
+    double acc = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) acc += C[i * d + j] * v[i] * v[j];
+    return 0.5 * acc;
+}
+
+/* Chirp with a symmetric matrix: u <- exp(-i x^T C x / 2) u. */
+static void apply_K_full(const grid_t *G, double *u, const double *C)
+{
+    for (long idx = 0; idx < G->total; ++idx) {
+        double x[3];
+        point_coords(G, idx, x, NULL);
+        mul_phase(u + 2 * idx, quad_form(G->ndim, C, x));
+    }
+}
+
+/* Drift with a symmetric matrix: FFT, u^ <- exp(-i k^T G k / 2) u^, inverse FFT. */
+static int apply_D_full(const grid_t *G, double *u, const double *Gm)
+{
+    int rc = orc_fftn(G->ndim, G->n, u, -1);
+    if (rc) return rc;
+    for (long idx = 0; idx < G->total; ++idx) {
+        double k[3];
+        point_coords(G, idx, NULL, k);
+        mul_phase(u + 2 * idx, quad_form(G->ndim, Gm, k));
+    }
+    return orc_fftn(G->ndim, G->n, u, +1);
+}
+
 /* B flow of the Fourier split (Eq. FourierSplit) frozen at tau: the harmonic
  * potential joins the pointwise phase,
  * u <- exp(-i dt w (sum_j mu omega_j(tau)^2 x_j^2/2 + eps V_I + sigma |u|^2)) u. */
@@ -542,6 +882,12 @@ static void apply_B_fsplit(const grid_t *G, double *u, double dt, double w, doub
         double harm = 0.0;
         for (int j = 0; j < G->ndim; ++j)
             harm += q[j] * axis_table(G, G->x2h, j)[axis_index(G, idx, j)];
+        if (par_coupled(G->par, G->ndim)) {  /* off-diagonal part of (mu/2) x^T W x */
+            double x[3];
+            point_coords(G, idx, x, NULL);
+            for (int i = 0; i < G->ndim; ++i)
+                for (int j = i + 1; j < G->ndim; ++j) harm += mu * par_wcross(G->par, i, j) * x[i] * x[j];
+        }
         double a2 = u[2 * idx] * u[2 * idx] + u[2 * idx + 1] * u[2 * idx + 1];
         mul_phase(u + 2 * idx, dt * w * (harm + G->vi[idx] + sig * a2));
     }
@@ -574,6 +920,24 @@ static int step_once(const grid_t *G, double *u, int m, const double *a, const d
     if (rule == ORC_FSPLIT) return step_fsplit(G, u, m, a, b, dt, tn);
     double tau = tn;
     apply_B(G, u, dt, b[0], tau);
+    if (par_coupled(G->par, G->ndim)) {  /* coupled trap: matrix chirps and drift */
+        const int d = G->ndim;
+        for (int i = 0; i < m; ++i) {
+            double F[18], Gm[18], E[18];
+            int nf = 0;
+            int rc = coupled_factors(rule, G->par, d, tau, a[i] * dt, F, Gm, E, &nf);
+            if (rc) return rc;
+            for (int h = 0; h < nf; ++h) {
+                apply_K_full(G, u, E + 9 * h);
+                rc = apply_D_full(G, u, Gm + 9 * h);
+                if (rc) return rc;
+                apply_K_full(G, u, F + 9 * h);
+            }
+            tau = tau + a[i] * dt;
+            apply_B(G, u, dt, b[i + 1], tau);
+        }
+        return ORC_OK;
+    }
     for (int i = 0; i < m; ++i) {
         double f[3], g[3], e[3];
         for (int j = 0; j < G->ndim; ++j) {
@@ -668,6 +1032,12 @@ int orc_energy(int ndim, const int *n, const double *lo, const double *hi, const
             long i = axis_index(&G, idx, j);
             k2h += axis_table(&G, G.k2h, j)[i];
             vh += mu * par_omega_sq(par, j, t) * axis_table(&G, G.x2h, j)[i];
+        }
+        if (par_coupled(par, ndim)) {  /* off-diagonal part of (mu/2) x^T W x */
+            double x[3];
+            point_coords(&G, idx, x, NULL);
+            for (int i = 0; i < ndim; ++i)
+                for (int j = i + 1; j < ndim; ++j) vh += mu * par_wcross(par, i, j) * x[i] * x[j];
         }
         double a2h = uh[2 * idx] * uh[2 * idx] + uh[2 * idx + 1] * uh[2 * idx + 1];
         ksum_add(&kin, k2h / mu * a2h);

@@ -47,6 +47,9 @@ class Instance:
     sigma: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
     eps: float = 0.0
     vfac: Tuple[Tuple[float, ...], ...] = (NO_V,) * 3
+    # constant off-diagonal W_xy, W_xz, W_yz of the squared-frequency matrix of a
+    # coupled trap V_HO = (mu/2) x^T W(t) x, W_jj = omega_j(t)^2
+    wcross: Tuple[float, float, float] = (0.0, 0.0, 0.0)
 
     @property
     def points(self) -> int:
