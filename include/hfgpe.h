@@ -126,6 +126,17 @@ typedef struct {
                                kind HFGPE_TF_SIN or HFGPE_TF_PULSE */
     double eps;             /* strength of V_I */
     hfgpe_vfactor v[3];     /* V_I factors; set c0 = 1, rest 0, for "no factor" */
+    double wcross[3];       /* coupled trap (d >= 2): constant off-diagonal entries
+                               W_xy, W_xz, W_yz of the squared-frequency matrix W(t)
+                               with W_jj = omega_j(t)^2; the trap is then
+                               (mu/2) x^T W(t) x, the general quadratic potential of
+                               Sec. 1.  Zero-initialise for a diagonal trap.  A plan
+                               whose instances use it must have it on all of them;
+                               rules: EXACT_CONST (omega constant; one drift per
+                               stage), CF4 (applied as its two exponentials: two
+                               drifts per stage) and FSPLIT; W(t) must stay positive
+                               definite.  The coupled drift k^T G k / 2 is not
+                               separable: a stage costs 2d - 1 axis passes. */
 } hfgpe_params;
 
 /* BAB composition of Eq. prod-gen: B(b_0) A(a_0) B(b_1) ... A(a_{m-1}) B(b_m).
@@ -207,6 +218,15 @@ int hfgpe_stage_coeffs(const hfgpe_plan *plan, int inst, double tn, double *out)
  * domain. */
 int hfgpe_stage_coeffs_params(const hfgpe_params *params, int ndim, const hfgpe_scheme *scheme,
                               double dt, double tn, double *out);
+
+/* Host-only testing hook for a coupled trap (params->wcross non-zero, ndim 2
+ * or 3): the factor triples K(F) D(G) K(E) of the step starting at tn, in the
+ * order they act (one per stage for EXACT_CONST and FSPLIT, two per stage for
+ * CF4), as out[(k*3 + {0: F, 1: G, 2: E}) * ndim*ndim + row*ndim + col], and
+ * their number in *ntriples.  out needs room for 2 * m * 3 * ndim^2 doubles.
+ * hfgpe_stage_coeffs returns INVALID_ARG for coupled plans. */
+int hfgpe_stage_coeffs_coupled(const hfgpe_params *params, int ndim, const hfgpe_scheme *scheme,
+                               double dt, double tn, double *out, int *ntriples);
 
 /* Named compositions: "leapfrog" (Eq. LeapFrogB), "lie", "srkn6_4",
  * "ni4_82", "ni5_84" (Table tab.1).  Writes m into *m and, when a and b are

@@ -28,6 +28,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "si
           -7: "non-finite coefficient", -8: "no gfx950 device"}
 SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", "hfgpe_evolve",
            "hfgpe_norm", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
+           "hfgpe_stage_coeffs_coupled",
            "hfgpe_scheme_preset",
            "hfgpe_device_status", "hfgpe_profile", "hfgpe_autotune", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
 
@@ -54,7 +55,7 @@ class VFactor(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("omega", TFunc * 3), ("sigma", TFunc),
-                ("eps", ctypes.c_double), ("v", VFactor * 3)]
+                ("eps", ctypes.c_double), ("v", VFactor * 3), ("wcross", ctypes.c_double * 3)]
 
 
 class Scheme(ctypes.Structure):
@@ -100,6 +101,9 @@ def load() -> ctypes.CDLL:
     lib.hfgpe_stage_coeffs_params.argtypes = [ctypes.POINTER(Params), ctypes.c_int,
                                               ctypes.POINTER(Scheme), ctypes.c_double,
                                               ctypes.c_double, dp]
+    lib.hfgpe_stage_coeffs_coupled.argtypes = [ctypes.POINTER(Params), ctypes.c_int,
+                                               ctypes.POINTER(Scheme), ctypes.c_double,
+                                               ctypes.c_double, dp, ctypes.POINTER(ctypes.c_int)]
     lib.hfgpe_scheme_preset.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), dp, dp]
     lib.hfgpe_device_status.argtypes = [vp]
     lib.hfgpe_profile.argtypes = [vp, dp, dp, i64p]
@@ -139,6 +143,22 @@ def stage_coeffs_params(inst, scheme: str, ho_rule: str, dt: float, tn: float) -
     return np.array(out[:]).reshape(len(a), inst.ndim, 3)
 
 
+def stage_coeffs_coupled(inst, scheme: str, ho_rule: str, dt: float, tn: float) -> np.ndarray:
+    """Factor triples (F, G, E) of a coupled-trap step by the library (host
+    only): shape (triples, 3, d, d), in the order they act."""
+    lib = load()
+    a, b = scheme_preset(scheme)
+    ca, cb = (ctypes.c_double * len(a))(*a), (ctypes.c_double * len(b))(*b)
+    sch = Scheme(len(a), ca, cb, *parse_rule(ho_rule))
+    d = inst.ndim
+    out = (ctypes.c_double * (2 * len(a) * 3 * d * d))()
+    nt = ctypes.c_int(0)
+    p = make_params(inst)
+    _check(lib.hfgpe_stage_coeffs_coupled(ctypes.byref(p), d, ctypes.byref(sch), float(dt), float(tn),
+                                          out, ctypes.byref(nt)), "hfgpe_stage_coeffs_coupled")
+    return np.array(out[: nt.value * 3 * d * d]).reshape(nt.value, 3, d, d)
+
+
 def make_grid(inst) -> Grid:
     g = Grid()
     g.ndim = inst.ndim
@@ -163,6 +183,8 @@ def make_params(inst) -> Params:
         p.v[j] = VFactor(*[float(v) for v in inst.vfac[j]])
     p.sigma = make_tfunc(inst.sigma)
     p.eps = float(inst.eps)
+    for j, v in enumerate(getattr(inst, "wcross", (0.0, 0.0, 0.0))):
+        p.wcross[j] = float(v)
     return p
 
 

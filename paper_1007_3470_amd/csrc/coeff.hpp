@@ -195,4 +195,132 @@ __host__ __device__ inline Fge fge_stage(int rule, double mu, const TFunc &om, d
     }
 }
 
+// ---------------------------------------------------------------------------
+// Coupled trap: H0 = p^2/(2 mu) + (mu/2) x^T W x with a symmetric d x d W
+// (d <= 3, row-major).  For a constant W the flow is, per normal mode w_k of
+// W = Q diag(w_k^2) Q^T, the flow of Lemma 2, so it factors as K(F) D(G) K(E)
+// with F = E = Q diag(mu w_k tan(w_k tau/2)) Q^T and G = Q diag(sin(w_k tau)/(mu w_k)) Q^T.
+// ---------------------------------------------------------------------------
+
+// cyclic Jacobi eigen-decomposition of a symmetric d x d matrix (A is overwritten)
+__host__ __device__ inline void jacobi_eig(int d, double *A, double *lam, double *Q)
+{
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) Q[i * d + j] = (i == j) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < d; ++i) {
+            diag += A[i * d + i] * A[i * d + i];
+            for (int j = i + 1; j < d; ++j) off += A[i * d + j] * A[i * d + j];
+        }
+        if (!(off > 1e-34 * diag)) break;
+        for (int p = 0; p < d; ++p)
+            for (int q = p + 1; q < d; ++q) {
+                const double apq = A[p * d + q];
+                if (apq == 0.0) continue;
+                const double th = (A[q * d + q] - A[p * d + p]) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < d; ++k) {
+                    const double akp = A[k * d + p], akq = A[k * d + q];
+                    A[k * d + p] = c * akp - sn * akq;
+                    A[k * d + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < d; ++k) {
+                    const double apk = A[p * d + k], aqk = A[q * d + k];
+                    A[p * d + k] = c * apk - sn * aqk;
+                    A[q * d + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < d; ++k) {
+                    const double qkp = Q[k * d + p], qkq = Q[k * d + q];
+                    Q[k * d + p] = c * qkp - sn * qkq;
+                    Q[k * d + q] = sn * qkp + c * qkq;
+                }
+            }
+    }
+    for (int i = 0; i < d; ++i) lam[i] = A[i * d + i];
+}
+
+// F (= E) and G of the exact constant-W flow over tau; 0, -3 (|w tau| >= pi for
+// some mode) or -4 (W not positive definite)
+__host__ __device__ inline int coupled_exact(int d, const double *W, double mu, double tau, double *F, double *G)
+{
+    double A[9], lam[3], Q[9], f[3], g[3];
+    for (int k = 0; k < d * d; ++k) A[k] = W[k];
+    jacobi_eig(d, A, lam, Q);
+    for (int k = 0; k < d; ++k) {
+        if (!(lam[k] > 0.0)) return -4;
+        const double w = sqrt(lam[k]);
+        if (!(fabs(w * tau) < M_PI)) return -3;
+        f[k] = mu * w * tan(0.5 * w * tau);
+        g[k] = sin(w * tau) / (mu * w);
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double qq = Q[i * d + k] * Q[j * d + k];
+                a += qq * f[k];
+                b += qq * g[k];
+            }
+            F[i * d + j] = a;
+            G[i * d + j] = b;
+        }
+    return 0;
+}
+
+// W(t) of instance I (d x d)
+__host__ __device__ inline void coupled_wmat(const InstDev &I, int d, double t, double *W)
+{
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            if (i == j) {
+                W[i * d + j] = tf_square(I.om[i], t);
+            } else {
+                const int a = i < j ? i : j, b = i < j ? j : i;
+                W[i * d + j] = I.wx[a + b - 1];  // (0,1) -> 0, (0,2) -> 1, (1,2) -> 2
+            }
+        }
+}
+
+// Factor triple number k of the step starting at tn for a coupled trap, as it
+// acts: exact (rule 0) one triple per stage; the commutator-free rule (1) two
+// triples per stage, the flow of W_R over half the stage then that of W_L (the
+// product of the two leaves the K(F) D(G) K(E) family for d >= 2); the Fourier
+// split (3) the free drift G = a_i dt / mu I with no chirps.  E = F except for
+// the Fourier split (both zero).  Returns 0 or a status code.
+__host__ __device__ inline int coupled_triple(const InstDev &I, const SchemeDev &S, double dt, double tn, int k,
+                                              double *F, double *G)
+{
+    const int d = I.ndim;
+    const int i = (S.rule == 1) ? (k >> 1) : k;
+    const double t0 = tn + dt * S.cum[i];
+    const double len = dt * S.a[i];
+    if (S.rule == 3) {
+        for (int a = 0; a < d * d; ++a) { F[a] = 0.0; G[a] = 0.0; }
+        for (int a = 0; a < d; ++a) G[a * d + a] = len / I.mu;
+        return 0;
+    }
+    double W[9];
+    if (S.rule == 0) {
+        coupled_wmat(I, d, t0, W);
+        return coupled_exact(d, W, I.mu, len, F, G);
+    }
+    if (S.rule == 1) {
+        const double r3 = 1.7320508075688772;
+        const double c1 = 0.5 - r3 / 6.0, c2 = 0.5 + r3 / 6.0;
+        const double al = 0.5 - 1.0 / r3, be = 1.0 - al;
+        double W1[9], W2[9];
+        coupled_wmat(I, d, t0 + c1 * len, W1);
+        coupled_wmat(I, d, t0 + c2 * len, W2);
+        const bool right = (k & 1) == 0;  // W_R acts first
+        for (int a = 0; a < d * d; ++a) W[a] = right ? (be * W1[a] + al * W2[a]) : (al * W1[a] + be * W2[a]);
+        return coupled_exact(d, W, I.mu, 0.5 * len, F, G);
+    }
+    return -1;
+}
+
+// effective stages per step of a coupled plan
+__host__ __device__ inline int coupled_stages(const SchemeDev &S) { return S.rule == 1 ? 2 * S.m : S.m; }
+
 }  // namespace hfgpe

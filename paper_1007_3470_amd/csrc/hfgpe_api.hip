@@ -75,6 +75,12 @@ struct hfgpe_plan {
     Rec *d_rec = nullptr;
     Rec *d_rec_open = nullptr;
     int rec_steps_cap = 0;
+    // coupled trap (off-diagonal W): records per effective stage and their
+    // off-diagonal parts
+    bool coupled = false;
+    int m_eff = 1;
+    RecX *d_recx = nullptr;
+    RecX *d_recx_open = nullptr;
     double *d_part = nullptr;
     double *d_kin = nullptr;
     int nblk = 1;
@@ -106,6 +112,8 @@ struct hfgpe_plan {
         if (d_err) (void)hipFree(d_err);
         if (d_rec) (void)hipFree(d_rec);
         if (d_rec_open) (void)hipFree(d_rec_open);
+        if (d_recx) (void)hipFree(d_recx);
+        if (d_recx_open) (void)hipFree(d_recx_open);
         if (d_part) (void)hipFree(d_part);
         if (d_kin) (void)hipFree(d_kin);
         if (d_vtab) (void)hipFree(d_vtab);
@@ -191,6 +199,62 @@ void tf_square_range(const hfgpe_tfunc &w, double &qmin, double &qmax, double &t
     if (w.freq != 0.0) t1 = 2.0 * M_PI / std::fabs(w.freq);
 }
 
+// Does instance p use off-diagonal W entries on its nd axes?
+bool params_coupled(const hfgpe_params &p, int nd)
+{
+    if (nd < 2) return false;
+    return p.wcross[0] != 0.0 || (nd == 3 && (p.wcross[1] != 0.0 || p.wcross[2] != 0.0));
+}
+
+// Coupled trap: rules, positive definiteness of W(t) over the reachable
+// frequency range (Gershgorin bound), the singular-step bound for the largest
+// normal frequency, and a sampled check of the factor triples.
+int validate_coupled(const hfgpe_params &p, int nd, const SchemeDev &S, double dt)
+{
+    for (int j = 0; j < 3; ++j)
+        if (!std::isfinite(p.wcross[j])) return HFGPE_E_INVALID_ARG;
+    if (S.rule != HFGPE_HO_EXACT_CONST && S.rule != HFGPE_HO_CF4 && S.rule != HFGPE_FSPLIT) return HFGPE_E_INVALID_ARG;
+    double amax = 0.0;
+    for (int i = 0; i < S.m; ++i) amax = std::max(amax, std::fabs(S.a[i]));
+    double lmax = 0.0, win0 = 0.0, win1 = 0.0;
+    for (int j = 0; j < nd; ++j) {
+        double qmin, qmax, w0, w1;
+        tf_square_range(p.omega[j], qmin, qmax, w0, w1);
+        if (S.rule == HFGPE_HO_EXACT_CONST && p.omega[j].amp != 0.0) return HFGPE_E_INVALID_ARG;
+        double off = 0.0;
+        for (int k = 0; k < nd; ++k)
+            if (k != j) off += std::fabs(p.wcross[j + k - 1]);
+        if (!(p.omega[j].v0 > 0.0) || !(qmin - off > 0.0)) return HFGPE_E_NONPOSITIVE_FREQ;
+        lmax = std::max(lmax, qmax + off);
+        if (w1 - w0 > win1 - win0) { win0 = w0; win1 = w1; }
+    }
+    if (S.rule == HFGPE_FSPLIT) return HFGPE_OK;
+    const double be = 0.5 + 1.0 / std::sqrt(3.0);  // largest weight of the averaged W
+    const double wmax = std::sqrt((S.rule == HFGPE_HO_CF4 ? be : 1.0) * lmax);
+    const double len = (S.rule == HFGPE_HO_CF4 ? 0.5 : 1.0) * amax * std::fabs(dt);
+    if (!(wmax * len < M_PI)) return HFGPE_E_SINGULAR;
+    InstDev I;
+    std::memset(&I, 0, sizeof(I));
+    I.ndim = nd;
+    I.mu = p.mu;
+    for (int j = 0; j < 3; ++j) {
+        I.om[j] = to_tf(p.omega[j]);
+        I.wx[j] = p.wcross[j];
+    }
+    for (int k = 0; k < 64; ++k) {
+        double t = win0 + (win1 - win0) * k / 64.0;
+        for (int e = 0; e < coupled_stages(S); ++e) {
+            double F[9], G[9];
+            int st = coupled_triple(I, S, dt, t, e, F, G);
+            if (st) return st;
+            for (int a = 0; a < nd * nd; ++a)
+                if (!std::isfinite(F[a]) || !std::isfinite(G[a])) return HFGPE_E_NONFINITE;
+        }
+        if (win1 == win0) break;
+    }
+    return HFGPE_OK;
+}
+
 // Conservative host-side validity check of every stage for the frequency
 // range an instance can reach, then a sampled check of the coefficients over
 // the modulation window.
@@ -207,6 +271,7 @@ int validate_instance(const hfgpe_params &p, int nd, const SchemeDev &S, double 
             !std::isfinite(v.k) || !std::isfinite(v.phi))
             return HFGPE_E_INVALID_ARG;
     }
+    if (params_coupled(p, nd)) return validate_coupled(p, nd, S, dt);
     if (S.rule == HFGPE_FSPLIT) return HFGPE_OK;  // free drift: no singular steps
     double amax = 0.0;
     for (int i = 0; i < S.m; ++i) amax = std::max(amax, std::fabs(S.a[i]));
@@ -341,15 +406,31 @@ constexpr int kGraphSteps = 16;
 static int nd_step(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const int *base, bool first,
                    bool profile)
 {
-    const int m = P->scheme.m;
+    const int m = P->m_eff, d = P->ndim;
+    // passes of one stage: (axis, kind); separable: one pass per axis; coupled
+    // (non-separable drift): forward along 0 .. d-2, forward + drift + inverse
+    // along d-1, inverse along d-2 .. 0
+    const bool full = P->coupled && P->scheme.rule != HFGPE_FSPLIT;
+    int pax[5], pkind[5], np = 0;
+    if (full) {
+        for (int j = 0; j < d - 1; ++j) { pax[np] = j; pkind[np++] = 1; }
+        pax[np] = d - 1; pkind[np++] = 2;
+        for (int j = d - 2; j >= 0; --j) { pax[np] = j; pkind[np++] = 3; }
+    } else {
+        for (int j = 0; j < d; ++j) { pax[np] = j; pkind[np++] = 0; }
+    }
     for (int i = 0; i < m; ++i)
-        for (int j = 0; j < P->ndim; ++j) {
+        for (int pp = 0; pp < np; ++pp) {
+            const int j = pax[pp];
             LaunchND L;
             std::memset(&L, 0, sizeof(L));
             L.insts = P->d_insts;
             L.n_inst = P->n_inst;
             L.rec = P->d_rec;
             L.rec_open = P->d_rec_open;
+            L.recx = P->d_recx;
+            L.recx_open = P->d_recx_open;
+            L.kind = pkind[pp];
             L.vtab = P->d_vtab;
             L.vtab_stride = P->vtab_stride;
             L.cistab = P->d_cistab;
@@ -365,8 +446,8 @@ static int nd_step(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const in
             L.rec_steps = rec_steps;
             L.step = step;
             L.step_base = base;
-            L.apply_open = (first && i == 0 && j == 0) ? 1 : 0;
-            L.apply_close = (j == P->ndim - 1) ? 1 : 0;
+            L.apply_open = (first && i == 0 && pp == 0) ? 1 : 0;
+            L.apply_close = (pp == np - 1) ? 1 : 0;
             L.grid = P->nd_grid;
             L.stream = P->stream;
             std::pair<hipEvent_t, hipEvent_t> es{};
@@ -516,6 +597,10 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         rc = validate_instance(params[k], nd, S, dt);
         if (rc) return rc;
     }
+    // a coupled trap changes the pass structure of the whole plan
+    bool coupled = n_inst > 0 && params_coupled(params[0], nd);
+    for (int k = 1; k < n_inst; ++k)
+        if (params_coupled(params[k], nd) != coupled) return HFGPE_E_INVALID_ARG;
     // d-D plans: every instance shares the grid shape (the boxes may differ)
     for (int k = 1; k < n_inst && nd > 1; ++k)
         for (int j = 0; j < 3; ++j)
@@ -568,6 +653,8 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         I.mu = p.mu;
         I.eps = p.eps;
         I.sig = to_tf(p.sigma);
+        for (int j = 0; j < 3; ++j) I.wx[j] = (nd >= 2) ? p.wcross[j] : 0.0;
+        I.coupled = coupled ? 1 : 0;
         P->offsets[k] = off;
         off += pts;
     }
@@ -583,7 +670,9 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
     int64_t maxpts = 0;
     for (auto &I : P->insts) maxpts = std::max<int64_t>(maxpts, (int64_t)I.n[0] * I.n[1] * I.n[2]);
     P->nblk = (int)std::min<int64_t>(kReduceBlocksMax, std::max<int64_t>(1, (maxpts + 4095) / 4096));
-    size_t per_step = (size_t)n_inst * S.m * sizeof(Rec);
+    P->coupled = coupled;
+    P->m_eff = coupled ? coupled_stages(S) : S.m;
+    size_t per_step = (size_t)n_inst * P->m_eff * (sizeof(Rec) + (coupled ? sizeof(RecX) : 0));
     P->rec_steps_cap = (int)std::max<size_t>(1, std::min<size_t>(kRecBudgetBytes / per_step, kRecStepsMax));
 
 #define ALLOC_TRY(ptr, bytes)                                      \
@@ -617,7 +706,11 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         COPY_TRY(P->d_err, &z, sizeof(int));
     }
     ALLOC_TRY(P->d_rec_open, sizeof(Rec) * n_inst);
-    ALLOC_TRY(P->d_rec, sizeof(Rec) * (size_t)n_inst * S.m * P->rec_steps_cap);
+    ALLOC_TRY(P->d_rec, sizeof(Rec) * (size_t)n_inst * P->m_eff * P->rec_steps_cap);
+    if (coupled) {
+        ALLOC_TRY(P->d_recx_open, sizeof(RecX) * n_inst);
+        ALLOC_TRY(P->d_recx, sizeof(RecX) * (size_t)n_inst * P->m_eff * P->rec_steps_cap);
+    }
     ALLOC_TRY(P->d_part, sizeof(double) * 4 * (size_t)n_inst * P->nblk);
     ALLOC_TRY(P->d_kin, sizeof(double) * n_inst);
     {
@@ -721,6 +814,8 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
         C.scheme = P->d_scheme;
         C.rec = P->d_rec;
         C.rec_open = P->d_rec_open;
+        C.recx = P->d_recx;
+        C.recx_open = P->d_recx_open;
         C.t0 = t0;
         C.dt = P->dt;
         C.step0 = s0;
@@ -902,9 +997,43 @@ int hfgpe_energy(hfgpe_plan *P, const void *d_psi, double t, double *h_out)
     return HFGPE_OK;
 }
 
+int hfgpe_stage_coeffs_coupled(const hfgpe_params *params, int ndim, const hfgpe_scheme *scheme, double dt,
+                               double tn, double *out, int *ntriples)
+{
+    if (!params || !out || !ntriples || ndim < 2 || ndim > 3 || !std::isfinite(tn) || !std::isfinite(dt) ||
+        dt == 0.0)
+        return HFGPE_E_INVALID_ARG;
+    SchemeDev S;
+    int rc = build_scheme(scheme, ndim, S);
+    if (rc) return rc;
+    if (S.rule != HFGPE_HO_EXACT_CONST && S.rule != HFGPE_HO_CF4 && S.rule != HFGPE_FSPLIT) return HFGPE_E_INVALID_ARG;
+    InstDev I;
+    std::memset(&I, 0, sizeof(I));
+    I.ndim = ndim;
+    I.mu = params->mu;
+    for (int j = 0; j < 3; ++j) {
+        I.om[j] = to_tf(params->omega[j]);
+        I.wx[j] = params->wcross[j];
+    }
+    const int me = coupled_stages(S), dd = ndim * ndim;
+    for (int k = 0; k < me; ++k) {
+        double F[9], G[9];
+        int st = coupled_triple(I, S, dt, tn, k, F, G);
+        if (st) return st;
+        for (int a = 0; a < dd; ++a) {
+            out[(k * 3 + 0) * dd + a] = F[a];
+            out[(k * 3 + 1) * dd + a] = G[a];
+            out[(k * 3 + 2) * dd + a] = F[a];
+        }
+    }
+    *ntriples = me;
+    return HFGPE_OK;
+}
+
 int hfgpe_stage_coeffs(const hfgpe_plan *P, int inst, double tn, double *out)
 {
     if (!P || !out || inst < 0 || inst >= P->n_inst || !std::isfinite(tn)) return HFGPE_E_INVALID_ARG;
+    if (P->coupled) return HFGPE_E_INVALID_ARG;  // see hfgpe_stage_coeffs_coupled
     const InstDev &I = P->insts[inst];
     const SchemeDev &S = P->scheme;
     for (int i = 0; i < S.m; ++i) {

@@ -13,6 +13,15 @@
 // the pencils first (coalesced rows of G elements) and LDS is interleaved by
 // pencil.  The drift factors of a thread's P wavenumbers are computed once per
 // (workgroup, instance) and reused for every pencil it processes.
+//
+// A coupled trap (off-diagonal W) has a full quadratic drift k^T G k / 2 that
+// no longer factors per axis.  A stage is then 2d - 1 passes: forward
+// transforms along the axes 0 .. d-2, one pass along the last axis that
+// transforms forward, applies the whole drift (the other wavenumbers are fixed
+// along a pencil) and transforms back, then inverse transforms along
+// d-2 .. 0, the last of which applies the merged closing x-phase.  The x-phase
+// carries the off-diagonal chirp terms along a pencil as a linear term in the
+// pass coordinate.
 #include <hip/hip_runtime.h>
 
 #include "coeff.hpp"
@@ -32,13 +41,18 @@ struct NdShape {
     int logn[3];
 };
 
-// MODE: 0 = drift only, 1 = closing x-phase after the drift, 2 = opening
-// x-phase before it (separate instantiations keep unused phase code out of
+// KIND of pass: separable stage along one axis, or (coupled trap) forward
+// transform only, forward + whole drift + inverse, inverse transform only.
+enum { kPassSep = 0, kPassFwd = 1, kPassMid = 2, kPassInv = 3 };
+
+// MODE: 0 = no x-phase, 1 = closing x-phase at the end of the pass, 2 = opening
+// x-phase at its start (separate instantiations keep unused phase code out of
 // the register allocation).
-template <typename Store, int P, int MAXS, int MODE, int TPB>
+template <typename Store, int P, int MAXS, int MODE, int TPB, int KIND>
 __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     const InstDev *__restrict__ insts, int n_inst, const Rec *__restrict__ rec,
-    const Rec *__restrict__ rec_open, const double *__restrict__ vtab, int vtab_stride,
+    const Rec *__restrict__ rec_open, const RecX *__restrict__ recx, const RecX *__restrict__ recx_open,
+    const double *__restrict__ vtab, int vtab_stride,
     const double2 *__restrict__ cistab, const double2 *__restrict__ twtab, int twlog,
     Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step_off,
     const int *__restrict__ step_base)
@@ -95,17 +109,19 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
         const int64_t g = gg - (int64_t)inst * gpi;
         const InstDev &I = insts[inst];
         const Rec &r = rec[((size_t)inst * rec_steps + step) * m + stage];
-        if (inst != kf_inst) {  // uniform across the workgroup
-            const double gk = r.g[axis], ks = I.kscale[axis];
-            __syncthreads();
-            for (int q = threadIdx.x; q < nj; q += blockDim.x) {
-                int sq = q - ((q >= (nj >> 1)) ? nj : 0);
-                double k = ks * (double)sq;
-                double2 f = cis_neg_tab(gk * (0.5 * k * k), ctab);
-                kfl[q] = make_double2(f.x * invN, f.y * invN);
+        if constexpr (KIND == kPassSep) {
+            if (inst != kf_inst) {  // uniform across the workgroup
+                const double gk = r.g[axis], ks = I.kscale[axis];
+                __syncthreads();
+                for (int q = threadIdx.x; q < nj; q += blockDim.x) {
+                    int sq = q - ((q >= (nj >> 1)) ? nj : 0);
+                    double k = ks * (double)sq;
+                    double2 f = cis_neg_tab(gk * (0.5 * k * k), ctab);
+                    kfl[q] = make_double2(f.x * invN, f.y * invN);
+                }
+                __syncthreads();
+                kf_inst = inst;
             }
-            __syncthreads();
-            kf_inst = inst;
         }
         // first element of this thread's pencil (offsets within an instance fit in 32 bits)
         int base;
@@ -125,17 +141,30 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
 
         // merged x-phase: along a pencil only the pass axis's coordinate varies, so
         // the other axes' chirp and V_I factors are formed once per pencil
-        auto xphase = [&](const Rec &q) {
-            double th0 = 0.0, v0 = I.eps;
+        auto xphase = [&](const Rec &q, const RecX *qx) {
+            double th0 = 0.0, v0 = I.eps, lin = 0.0;
+            double xo[3] = {0.0, 0.0, 0.0};  // coordinates of the pencil off the pass axis
             int shift = 0;
             for (int j = 0; j < sh.ndim; ++j) {
                 if (j != axis) {
                     int i = (base >> shift) & (sh.n[j] - 1);
                     double x = I.lo[j] + (double)i * I.dx[j];
+                    xo[j] = x;
                     th0 = fma(q.chi[j], 0.5 * x * x, th0);
                     v0 *= vtab[((size_t)inst * 3 + j) * vtab_stride + i];
                 }
                 shift += sh.logn[j];
+            }
+            if (qx) {  // off-diagonal chirp: sum_{i<j} C_ij x_i x_j
+#pragma unroll
+                for (int pr = 0; pr < 3; ++pr) {
+                    const int a = (pr == 2) ? 1 : 0, b = (pr == 0) ? 1 : 2;
+                    if (b >= sh.ndim) continue;
+                    const double c = qx->chix[pr];
+                    if (a == axis) lin = fma(c, xo[b], lin);
+                    else if (b == axis) lin = fma(c, xo[a], lin);
+                    else th0 = fma(c, xo[a] * xo[b], th0);
+                }
             }
             const double chia = q.chi[axis], loa = I.lo[axis], dxa = I.dx[axis];
             const double *va = vtab + ((size_t)inst * 3 + axis) * vtab_stride;
@@ -145,7 +174,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
                 const int i = tl + c * T;
                 const double x = loa + (double)i * dxa;
                 double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
-                double th = fma(chia, 0.5 * x * x, fma(wv0, va[i], fma(q.s, a2, th0)));
+                double th = fma(x, fma(chia, 0.5 * x, lin), fma(wv0, va[i], fma(q.s, a2, th0)));
                 u[c] = cmul(u[c], cis_neg_tab(th, ctab));
                 // keep the scheduler from interleaving all P phase evaluations
                 // (register pressure); pairs still overlap
@@ -153,12 +182,52 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
             }
         };
 
-        if constexpr (MODE == 2) xphase(rec_open[inst]);
-        fft.template run<-1>(u);
+        if constexpr (MODE == 2) xphase(rec_open[inst], recx_open ? recx_open + inst : nullptr);
+        if constexpr (KIND != kPassInv) fft.template run<-1>(u);
+        if constexpr (KIND == kPassSep) {
 #pragma unroll
-        for (int c = 0; c < P; ++c) u[c] = cmul(u[c], kfl[tl + c * T]);
-        fft.template run<+1>(u);
-        if constexpr (MODE == 1) xphase(r);
+            for (int c = 0; c < P; ++c) u[c] = cmul(u[c], kfl[tl + c * T]);
+        }
+        if constexpr (KIND == kPassMid) {
+            // whole drift k^T G k / 2 with the other wavenumbers of the pencil
+            // fixed: c0 + k_a (c1 + G_aa k_a / 2); scaled by 1 / N_total
+            const RecX &qx = recx[((size_t)inst * rec_steps + step) * m + stage];
+            double ko[3] = {0.0, 0.0, 0.0};
+            double scale = invN;
+            int shift = 0;
+            for (int j = 0; j < sh.ndim; ++j) {
+                if (j != axis) {
+                    const int i = (base >> shift) & (sh.n[j] - 1);
+                    const int sq = i - ((i >= (sh.n[j] >> 1)) ? sh.n[j] : 0);
+                    ko[j] = I.kscale[j] * (double)sq;
+                    scale *= 1.0 / (double)sh.n[j];
+                }
+                shift += sh.logn[j];
+            }
+            double c0 = 0.0, c1 = 0.0;
+            for (int j = 0; j < sh.ndim; ++j)
+                if (j != axis) c0 = fma(r.g[j], 0.5 * ko[j] * ko[j], c0);
+#pragma unroll
+            for (int pr = 0; pr < 3; ++pr) {
+                const int a = (pr == 2) ? 1 : 0, b = (pr == 0) ? 1 : 2;
+                if (b >= sh.ndim) continue;
+                const double g = qx.gx[pr];
+                if (a == axis) c1 = fma(g, ko[b], c1);
+                else if (b == axis) c1 = fma(g, ko[a], c1);
+                else c0 = fma(g, ko[a] * ko[b], c0);
+            }
+            const double gaa = r.g[axis], ksa = I.kscale[axis];
+#pragma unroll
+            for (int c = 0; c < P; ++c) {
+                const int q = tl + c * T;
+                const int sq = q - ((q >= (nj >> 1)) ? nj : 0);
+                const double k = ksa * (double)sq;
+                const double2 f = cis_neg_tab(fma(k, fma(gaa, 0.5 * k, c1), c0), ctab);
+                u[c] = cmul(u[c], make_double2(f.x * scale, f.y * scale));
+            }
+        }
+        if constexpr (KIND != kPassFwd) fft.template run<+1>(u);
+        if constexpr (MODE == 1) xphase(r, recx ? recx + ((size_t)inst * rec_steps + step) * m + stage : nullptr);
 #pragma unroll
         for (int c = 0; c < P; ++c) u0[(tl + c * T) * estr] = from_d2<Store>(u[c]);
     }
@@ -279,32 +348,46 @@ int nd_threads(const int *n, int axis, int c64)
     return (lg256 < 3 && nd_group_log(n, axis, 512) > lg256) ? 512 : kThreadsND;
 }
 
-template <typename Store, int P, int MAXS, int MODE, int TPB>
+template <typename Store, int P, int MAXS, int MODE, int TPB, int KIND>
 static hipError_t launch_pass_tpb(const LaunchND &L)
 {
     NdShape sh = make_shape(L);
     int lG = nd_group_log(L.n, L.axis, TPB);
     int threads = 1 << (lG + sh.logn[L.axis] - Log2<P>::value);
-    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE, TPB>), dim3(L.grid), dim3(threads), 0, L.stream, L.insts,
-                       L.n_inst, L.rec, L.rec_open, L.vtab, L.vtab_stride, L.cistab, L.twtab, L.twlog,
-                       (Store *)L.psi, sh, L.axis, lG, L.stage, L.m, L.rec_steps, L.step, L.step_base);
+    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE, TPB, KIND>), dim3(L.grid), dim3(threads), 0, L.stream,
+                       L.insts, L.n_inst, L.rec, L.rec_open, L.recx, L.recx_open, L.vtab, L.vtab_stride, L.cistab,
+                       L.twtab, L.twlog, (Store *)L.psi, sh, L.axis, lG, L.stage, L.m, L.rec_steps, L.step,
+                       L.step_base);
     return hipGetLastError();
 }
 
 template <typename Store, int P, int MAXS, int MODE>
 static hipError_t launch_pass_mode(const LaunchND &L)
 {
-    if constexpr (P == 8 && sizeof(Store) == 8) {
-        if (nd_threads(L.n, L.axis, 1) == 512) return launch_pass_tpb<Store, P, MAXS, MODE, 512>(L);
+    switch (L.kind) {
+    case kPassSep:
+        if constexpr (P == 8 && sizeof(Store) == 8) {
+            if (nd_threads(L.n, L.axis, 1) == 512) return launch_pass_tpb<Store, P, MAXS, MODE, 512, kPassSep>(L);
+        }
+        return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassSep>(L);
+    case kPassFwd:
+        if constexpr (MODE != 1) return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassFwd>(L);
+        return hipErrorInvalidValue;
+    case kPassMid:
+        if constexpr (MODE == 0) return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassMid>(L);
+        return hipErrorInvalidValue;
+    case kPassInv:
+        if constexpr (MODE != 2) return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassInv>(L);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
     }
-    return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND>(L);
 }
 
 template <typename Store, int P, int MAXS>
 static hipError_t launch_pass_p(const LaunchND &L)
 {
-    // an evolve call opens on the first x pass and closes every stage on the
-    // last axis; with d >= 2 these never fall on the same pass
+    // an evolve call opens on the first pass of axis 0 and closes every stage
+    // on its last pass; with d >= 2 these never fall on the same pass
     if (L.apply_open && L.apply_close) return hipErrorInvalidValue;
     if (L.apply_close) return launch_pass_mode<Store, P, MAXS, 1>(L);
     if (L.apply_open) return launch_pass_mode<Store, P, MAXS, 2>(L);

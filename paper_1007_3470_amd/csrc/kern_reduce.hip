@@ -50,14 +50,17 @@ __global__ __launch_bounds__(256) void reduce_kernel(const InstDev *__restrict__
         a.add(a2);
         if (energy) {
             int64_t rest = idx;
-            double V = 0.0, VI = 1.0;
+            double V = 0.0, VI = 1.0, xs[3] = {0.0, 0.0, 0.0};
             for (int j = 0; j < nd; ++j) {
                 int i = (int)(rest & (I.n[j] - 1));
                 rest >>= I.logn[j];
                 double x = I.lo[j] + (double)i * I.dx[j];
+                xs[j] = x;
                 V += hw[j] * x * x;
                 VI *= vfactor(I.vf[j], x);
             }
+            if (I.coupled)  // off-diagonal part of (mu/2) x^T W x
+                V += I.mu * (I.wx[0] * xs[0] * xs[1] + I.wx[1] * xs[0] * xs[2] + I.wx[2] * xs[1] * xs[2]);
             V += I.eps * VI;
             b.add(V * a2);
             c.add(0.5 * sig * a2 * a2);

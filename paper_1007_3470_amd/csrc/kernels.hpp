@@ -12,8 +12,10 @@ struct LaunchCoeff {
     const InstDev *insts;
     int n_inst;
     const SchemeDev *scheme;  // device copy
-    Rec *rec;                 // [n_inst][k_steps][m]
+    Rec *rec;                 // [n_inst][k_steps][m] (coupled trap: m effective stages)
     Rec *rec_open;            // [n_inst]
+    RecX *recx;               // coupled trap: off-diagonal parts, same layout; else null
+    RecX *recx_open;
     double t0, dt;
     int64_t step0;            // global index of the chunk's first step
     int k_steps;              // steps in this chunk
@@ -85,6 +87,9 @@ struct LaunchND {
     int n_inst;
     const Rec *rec;
     const Rec *rec_open;
+    const RecX *recx;       // coupled trap: off-diagonal G and chirp entries, else null
+    const RecX *recx_open;
+    int kind;               // 0 separable stage pass, 1 forward only, 2 forward + whole drift + inverse, 3 inverse only
     const double *vtab;  // [n_inst][3][vtab_stride]: V_I factor of each axis on its grid
     int vtab_stride;
     const double2 *cistab;

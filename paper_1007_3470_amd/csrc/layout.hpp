@@ -37,6 +37,9 @@ struct InstDev {
     TFunc om[3];
     TFunc sig;
     VFac vf[3];
+    double wx[3];  // coupled trap: constant W_xy, W_xz, W_yz of (mu/2) x^T W x
+    int coupled;   // 1 when some wx used by the grid's axes is non-zero
+    int pad2_;
 };
 
 // The pointwise x-space phase applied after stage i of a step:
@@ -49,6 +52,13 @@ struct Rec {
     double chi[3];
     double w;
     double s;
+};
+
+// Off-diagonal entries (xy, xz, yz) of the drift matrix G and of the merged
+// chirp matrix of a coupled trap, beside the Rec of the same stage.
+struct RecX {
+    double gx[3];
+    double chix[3];
 };
 
 // Composition in device-friendly form (Eq. prod-gen; b has m+1 weights;

@@ -204,3 +204,56 @@ def test_null_arguments_rejected():
     assert lib.hfgpe_norm(None, None, None) == -1
     assert lib.hfgpe_instance_offsets(None, None) == -1
     assert lib.hfgpe_stage_coeffs(None, 0, 0.0, None) == -1
+
+
+# ---------------------------------------------------------------------------
+# coupled trap (off-diagonal W): library factor triples vs the oracle's 2d x 2d route
+# ---------------------------------------------------------------------------
+def _coupled_inst(d, mu=1.2, const=False, wc=(0.3, 0.2, -0.25)):
+    om = ((1.2, 0.0 if const else 0.2, 1.5, 0.3), (0.9, 0.0, 0.0, 0.0),
+          (1.4, 0.0 if const else 0.1, 0.7, 0.0))
+    nn = tuple([8] * d + [1] * (3 - d))
+    return W.Instance(d, nn, tuple([-2.0] * d + [0.0] * (3 - d)), tuple([2.0] * d + [1.0] * (3 - d)),
+                      mu=mu, omega=om, wcross=wc)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("rule", ["exact_const", "cf4"])
+@pytest.mark.parametrize("scheme,dt", [("leapfrog", 0.05), ("ni5_84", -0.1), ("srkn6_4", 0.2)])
+def test_coupled_triples_match_oracle(d, rule, scheme, dt):
+    for mu, tn in ((1.0, 0.0), (1.7, 1.3)):
+        inst = _coupled_inst(d, mu=mu, const=(rule == "exact_const"))
+        lib_t = pkg.stage_coeffs_coupled(inst, scheme, rule, dt, tn)
+        orc_t = oracle.stage_coeffs_full(inst, scheme, rule, dt, tn)
+        assert lib_t.shape == orc_t.shape
+        scale = np.abs(orc_t).max()
+        assert np.abs(lib_t - orc_t).max() < 1e-13 * scale, np.abs(lib_t - orc_t).max()
+
+
+def test_coupled_fsplit_triples():
+    inst = _coupled_inst(2, mu=1.5)
+    t = pkg.stage_coeffs_coupled(inst, "ni4_82", "fsplit", 0.1, 0.4)
+    a, _ = oracle.scheme_coefficients("ni4_82")
+    assert t.shape == (4, 3, 2, 2)
+    for k in range(4):
+        assert not t[k, 0].any() and not t[k, 2].any()
+        assert np.array_equal(t[k, 1], np.eye(2) * (a[k] * 0.1 / 1.5))
+
+
+def test_coupled_validation():
+    base = W.gpe_2d(n=16, n_inst=1, nsteps=0).instances[0]
+    cpl = replace(base, wcross=(0.2, 0.0, 0.0))
+    assert _gpu_or_nodevice(_create([cpl], rule="cf4"))
+    assert _gpu_or_nodevice(_create([cpl], rule="fsplit"))
+    assert _create([cpl], rule="magnus6") == -1                      # rule not written for coupled W
+    assert _create([cpl], rule="fundamental") == -1
+    assert _create([cpl], rule="exact_const") == -1                  # omega_y varies in time
+    const = replace(cpl, omega=((1.0, 0.0, 0.0, 0.0), (1.5, 0.0, 0.0, 0.0), W.CONST_OMEGA))
+    assert _gpu_or_nodevice(_create([const], rule="exact_const", dt=1.0))
+    assert _create([const], rule="exact_const", dt=3.0) == -3        # beyond the first zero of G
+    assert _create([cpl, base], rule="cf4") == -1                    # mixed coupled / diagonal plan
+    assert _create([replace(cpl, wcross=(5.0, 0.0, 0.0))], rule="cf4") == -4   # W indefinite
+    assert _create([replace(cpl, wcross=(float("nan"), 0.0, 0.0))], rule="cf4") == -1
+    # a 1-D instance ignores wcross
+    c1 = replace(W.gpe_1d(n=64, nsteps=0).instances[0], wcross=(0.5, 0.0, 0.0))
+    assert _gpu_or_nodevice(_create([c1]))

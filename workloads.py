@@ -249,6 +249,35 @@ def timedep_1d(form: str = "cos", n: int = 1024, T: float = 5.0, nsteps: int = 5
                     notes="%s trap, N=%d on [-20,20), T=%g" % (form, n, T))
 
 
+# ---------------------------------------------------------------------------
+# Coupled traps (off-diagonal W, Sec. 1's general x^T M x): the 2-D and 3-D
+# GPE recipes above with constant cross terms, W(t) positive definite
+# (Gershgorin) over the whole modulation.
+# ---------------------------------------------------------------------------
+def coupled_2d(n: int = 512, n_inst: int = 16, lo: float = -12.0, hi: float = 12.0,
+               dt: float = 5e-4, nsteps: int = 2000, seed: int = 34704, scheme: str = "leapfrog",
+               rule: str = "cf4", wxy: float = 0.4, constant: bool = False) -> Workload:
+    w = gpe_2d(n=n, n_inst=n_inst, lo=lo, hi=hi, dt=dt, nsteps=nsteps, seed=seed, scheme=scheme,
+               rule=rule)
+    insts = []
+    for inst in w.instances:
+        om = inst.omega
+        if constant:
+            om = ((om[0][0], 0.0, 0.0, 0.0), (om[1][0], 0.0, 0.0, 0.0), CONST_OMEGA)
+        insts.append(replace(inst, omega=om, wcross=(wxy, 0.0, 0.0)))
+    return replace(w, name="coupled_2d", instances=insts,
+                   notes=w.notes + ", W_xy=%g%s" % (wxy, ", constant omega" if constant else ""))
+
+
+def coupled_3d(n: int = 256, lo: float = -8.0, hi: float = 8.0, dt: float = 1e-3,
+               nsteps: int = 500, seed: int = 34705, scheme: str = "ni5_84", rule: str = "cf4",
+               wcross=(0.3, 0.2, -0.25)) -> Workload:
+    w = gpe_3d(n=n, lo=lo, hi=hi, dt=dt, nsteps=nsteps, seed=seed, scheme=scheme, rule=rule)
+    inst = replace(w.instances[0], wcross=tuple(wcross))
+    return replace(w, name="coupled_3d", instances=[inst],
+                   notes=w.notes + ", W_offdiag=%s" % (tuple(wcross),))
+
+
 CONFIGS = {
     "coherent_1d": coherent_1d,
     "gpe_1d": gpe_1d,
@@ -257,6 +286,8 @@ CONFIGS = {
     "gpe_3d": gpe_3d,
     "perturbed_1d": perturbed_1d,
     "timedep_1d": timedep_1d,
+    "coupled_2d": coupled_2d,
+    "coupled_3d": coupled_3d,
 }
 
 
