@@ -260,10 +260,11 @@ def main(argv=None):
     pkg.load()
     K, WU = args.steps, args.warmup
     nd_kw = {"nsteps": args.nd_steps} if args.nd_steps > 0 else {}
+    nd_sets = (("gpe_2d", W.gpe_2d), ("gpe_3d", W.gpe_3d), ("coupled_2d", W.coupled_2d),
+               ("coupled_3d", W.coupled_3d))
     if args.nd_only:
-        print(json.dumps({"other_workloads": {"gpe_2d": nd_workload(pkg, torch, W, W.gpe_2d(**nd_kw), 8),
-                                              "gpe_3d": nd_workload(pkg, torch, W, W.gpe_3d(**nd_kw), 8)}}),
-              flush=True)
+        print(json.dumps({"other_workloads": {name: nd_workload(pkg, torch, W, gen(**nd_kw), 8)
+                                              for name, gen in nd_sets}}), flush=True)
         return 0
     w = W.batch_1d(nsteps=K)
     npts = w.points
@@ -319,8 +320,7 @@ def main(argv=None):
         "wall_s": {"c64": wall64, "c128": wall128},
     }
     if not args.no_nd:
-        line["other_workloads"] = {"gpe_2d": nd_workload(pkg, torch, W, W.gpe_2d(**nd_kw), 8),
-                                   "gpe_3d": nd_workload(pkg, torch, W, W.gpe_3d(**nd_kw), 8)}
+        line["other_workloads"] = {name: nd_workload(pkg, torch, W, gen(**nd_kw), 8) for name, gen in nd_sets}
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -117,3 +117,40 @@ def test_coupled_norm_energy(pkg, dtype):
             assert abs(nrm[k] - oracle.norm(inst, got[k])) < 1e-12 * max(1, abs(nrm[k]))
             ref = oracle.energy(inst, got[k], t)
             assert np.allclose(en[k], ref, rtol=1e-11, atol=1e-11), (en[k], ref)
+
+
+# ---------------------------------------------------------------------------
+# full sizes, in the launch configuration of the solver (graph replay)
+# ---------------------------------------------------------------------------
+def test_coupled_2d_full_size(pkg):
+    w = W.coupled_2d()   # 16 x 512^2, leapfrog + cf4 (two drifts per stage), 2000 steps
+    _, _, short = run_gpu(pkg, w, "c128", nsteps=40, use_graph=True)
+    ref = oracle.evolve(w.instances[3], w.psi0[3], w.scheme, w.ho_rule, w.dt, w.t0, 40)
+    err = W.rel_l2(short[3], ref)
+    say("coupled 2d full size, 40 steps, instance 3 vs oracle: %.3e" % err)
+    assert err < 1e-11
+    p128, b128, full128 = run_gpu(pkg, w, "c128", use_graph=True)
+    p64, b64, full64 = run_gpu(pkg, w, "c64", use_graph=True)
+    n0 = np.array([oracle.norm(i, p) for i, p in zip(w.instances, w.psi0)])
+    drift = np.abs(p128.norm(b128) - n0).max()
+    e64 = max(W.rel_l2(a, b) for a, b in zip(full64, full128))
+    say("coupled 2d full 2000 steps: c128 norm drift %.3e, c64 vs c128 max %.3e" % (drift, e64))
+    assert drift < 1e-11 and e64 < 5e-5
+
+
+def test_coupled_3d_full_size(pkg):
+    # oracle parity on the same recipe at 128^3 (one 256^3 oracle step takes ~45 s);
+    # at 256^3: norm conservation and c64 against c128 over the full run
+    half = W.coupled_3d(n=128)
+    _, _, one = run_gpu(pkg, half, "c128", nsteps=1)
+    ref = oracle.evolve(half.instances[0], half.psi0[0], half.scheme, half.ho_rule, half.dt, half.t0, 1)
+    err = W.rel_l2(one[0], ref)
+    say("coupled 3d 128^3, 1 step vs oracle: %.3e" % err)
+    assert err < 1e-11
+    w = W.coupled_3d()   # 256^3, NI5 + cf4, 500 steps
+    p128, b128, full128 = run_gpu(pkg, w, "c128", use_graph=True)
+    p64, b64, full64 = run_gpu(pkg, w, "c64", use_graph=True)
+    drift = abs(p128.norm(b128)[0] - oracle.norm(w.instances[0], w.psi0[0]))
+    e64 = W.rel_l2(full64[0], full128[0])
+    say("coupled 3d full 500 steps: c128 norm drift %.3e, c64 vs c128 %.3e" % (drift, e64))
+    assert drift < 1e-11 and e64 < 5e-5
