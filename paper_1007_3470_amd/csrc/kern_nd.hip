@@ -104,9 +104,56 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     const int64_t total = (int64_t)n_inst * gpi;
     const int64_t per = (total + gridDim.x - 1) / gridDim.x;
     const int64_t g_end = (blockIdx.x + 1) * per < total ? (blockIdx.x + 1) * per : total;
-    for (int64_t gg = blockIdx.x * per; gg < g_end; ++gg) {
-        const int inst = (int)(gg / gpi);
-        const int64_t g = gg - (int64_t)inst * gpi;
+    const int estr = (axis == 0) ? 1 : (1 << lstride);
+    // instance and first element of this thread's pencil in group gq (offsets
+    // within an instance fit in 32 bits)
+    auto locate = [&](int64_t gq, int &inst_q, int &base_q) {
+        inst_q = (int)(gq / gpi);
+        const int64_t g = gq - (int64_t)inst_q * gpi;
+        if (axis == 0) {
+            base_q = (int)(((g << lG) + slot) << lnj);
+        } else {
+            const int64_t ipo = ((int64_t)1 << lstride) >> lG;  // groups per outer index
+            const int inner = (int)((g % ipo) * G + slot);
+            const int outer = (int)(g / ipo);
+            base_q = outer * (nj << lstride) + inner;
+        }
+    };
+    // c64: the next group's points are loaded while the current one is
+    // transformed (the 16 extra registers fit; for c128 the 32 they would take
+    // cost more in spills than the hidden latency gains)
+    constexpr bool kPrefetch = sizeof(Store) == 8;
+    Store nxt[kPrefetch ? P : 1];
+    int inst_n = 0, base_n = 0;
+    const int64_t g_begin = blockIdx.x * per;
+    if constexpr (kPrefetch) {
+        if (g_begin < g_end) {
+            locate(g_begin, inst_n, base_n);
+            const Store *src = psi + insts[inst_n].offset + base_n;
+#pragma unroll
+            for (int c = 0; c < P; ++c) nxt[c] = src[(tl + c * T) * estr];
+        }
+    }
+    for (int64_t gg = g_begin; gg < g_end; ++gg) {
+        double2 u[P];
+        int inst, base;
+        if constexpr (kPrefetch) {
+            inst = inst_n;
+            base = base_n;
+#pragma unroll
+            for (int c = 0; c < P; ++c) u[c] = to_d2(nxt[c]);
+            if (gg + 1 < g_end) {
+                locate(gg + 1, inst_n, base_n);
+                const Store *src = psi + insts[inst_n].offset + base_n;
+#pragma unroll
+                for (int c = 0; c < P; ++c) nxt[c] = src[(tl + c * T) * estr];
+            }
+        } else {
+            locate(gg, inst, base);
+            const Store *src = psi + insts[inst].offset + base;
+#pragma unroll
+            for (int c = 0; c < P; ++c) u[c] = to_d2(src[(tl + c * T) * estr]);
+        }
         const InstDev &I = insts[inst];
         const Rec &r = rec[((size_t)inst * rec_steps + step) * m + stage];
         if constexpr (KIND == kPassSep) {
@@ -123,21 +170,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
                 kf_inst = inst;
             }
         }
-        // first element of this thread's pencil (offsets within an instance fit in 32 bits)
-        int base;
-        if (axis == 0) {
-            base = (int)(((g << lG) + slot) << lnj);
-        } else {
-            const int64_t ipo = ((int64_t)1 << lstride) >> lG;  // groups per outer index
-            const int inner = (int)((g % ipo) * G + slot);
-            const int outer = (int)(g / ipo);
-            base = outer * (nj << lstride) + inner;
-        }
-        const int estr = (axis == 0) ? 1 : (1 << lstride);
         Store *u0 = psi + I.offset + base;
-        double2 u[P];
-#pragma unroll
-        for (int c = 0; c < P; ++c) u[c] = to_d2(u0[(tl + c * T) * estr]);
 
         // merged x-phase: along a pencil only the pass axis's coordinate varies, so
         // the other axes' chirp and V_I factors are formed once per pencil
