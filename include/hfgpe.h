@@ -194,6 +194,17 @@ int hfgpe_instance_offsets(const hfgpe_plan *plan, int64_t *off);
  * nsteps = 0 does nothing. */
 int hfgpe_evolve(hfgpe_plan *plan, void *d_psi, double t0, int64_t nsteps);
 
+/* Perturbation as a device array (Sec. 1: V_I is any potential; the B flow of
+ * Lemma 1 is pointwise): d_vi holds eps V_I(x) in FP64 at every grid point of
+ * every instance, in the packed layout of the state (hfgpe_instance_offsets),
+ * and replaces the instances' eps and per-axis factors in hfgpe_evolve and
+ * hfgpe_energy.  NULL restores the factor form.  The caller owns the buffer
+ * and keeps it alive and unchanged while work that uses it may run on the
+ * plan's stream.  Costs one extra read of 8 bytes per point wherever the
+ * x-space phase is applied (every step of the 1-D kernel reads it once per
+ * chunk into LDS).  Errors: INVALID_ARG (plan NULL). */
+int hfgpe_set_potential(hfgpe_plan *plan, const double *d_vi);
+
 /* Discrete squared norm h^d sum |u|^2 of every instance into the host array
  * h_out[n_inst] (FP64, compensated summation).  Synchronises the stream. */
 int hfgpe_norm(hfgpe_plan *plan, const void *d_psi, double *h_out);

@@ -76,14 +76,14 @@ def _lib():
                                          ctypes.c_int, ctypes.c_double, ctypes.c_double, dp]
         lib.orc_evolve.argtypes = [ctypes.c_int, ip, dp, dp, dp, ctypes.c_int, dp, dp,
                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_long, dp]
+                                   ctypes.c_long, dp, dp]
         lib.orc_drift.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp]
         lib.orc_stage_matrix_full.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_double,
                                               ctypes.c_double, dp]
         lib.orc_stage_coeffs_full.argtypes = [ctypes.c_int, dp, ctypes.c_int, dp, ctypes.c_int,
                                               ctypes.c_double, ctypes.c_double, dp, ip]
         lib.orc_norm.argtypes = [ctypes.c_int, ip, dp, dp, dp, dp]
-        lib.orc_energy.argtypes = [ctypes.c_int, ip, dp, dp, dp, ctypes.c_double, dp, dp]
+        lib.orc_energy.argtypes = [ctypes.c_int, ip, dp, dp, dp, ctypes.c_double, dp, dp, dp]
         assert lib.orc_npar() == NPAR
         _LIB = lib
     return _LIB
@@ -221,16 +221,26 @@ def stage_coeffs(inst, scheme: str, rule: str, dt: float, tn: float) -> np.ndarr
     return out.reshape(len(a), inst.ndim, 3)
 
 
+def _vi_ptr(inst, vi):
+    if vi is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(vi, dtype=np.float64).reshape(inst.shape))
+    return arr, _dp(arr)
+
+
 def evolve(inst, psi: np.ndarray, scheme: str, rule: str, dt: float, t0: float,
-           nsteps: int) -> np.ndarray:
-    """Advance one instance ``nsteps`` steps of size ``dt`` from ``t0``."""
+           nsteps: int, vi=None) -> np.ndarray:
+    """Advance one instance ``nsteps`` steps of size ``dt`` from ``t0``.  ``vi``
+    (optional, shape of the grid) gives eps V_I at every point and replaces
+    the instance's factor form."""
     a, b = scheme_coefficients(scheme)
     a, b = np.array(a), np.array(b)
     n, lo, hi = _grid_arrays(inst)
     out = _as_c128(psi)
+    keep, vp = _vi_ptr(inst, vi)
     _check(_lib().orc_evolve(inst.ndim, _ip(n), _dp(lo), _dp(hi), _dp(params_block(inst)),
                              len(a), _dp(a), _dp(b), *rule_id(rule), float(dt), float(t0),
-                             int(nsteps), _dp(out.view(np.float64))))
+                             int(nsteps), vp, _dp(out.view(np.float64))))
     return out
 
 
@@ -255,11 +265,13 @@ def norm(inst, psi: np.ndarray) -> float:
     return float(out[0])
 
 
-def energy(inst, psi: np.ndarray, t: float) -> np.ndarray:
-    """[total, kinetic, potential, interaction] energy at time t."""
+def energy(inst, psi: np.ndarray, t: float, vi=None) -> np.ndarray:
+    """[total, kinetic, potential, interaction] energy at time t (``vi`` as in
+    ``evolve``)."""
     n, lo, hi = _grid_arrays(inst)
     z = _as_c128(psi)
     out = np.zeros(4)
+    keep, vp = _vi_ptr(inst, vi)
     _check(_lib().orc_energy(inst.ndim, _ip(n), _dp(lo), _dp(hi), _dp(params_block(inst)),
-                             float(t), _dp(z.view(np.float64)), _dp(out)))
+                             float(t), vp, _dp(z.view(np.float64)), _dp(out)))
     return out

@@ -51,6 +51,8 @@
  *   [18+6j..23+6j] V_I factor of axis j: c0, c2, c4, gs, k, phi
  *                  v_j(x) = (c0 + c2 x^2 + c4 x^4) * (gs > 0 ? exp(-x^2/gs) : 1)
  *                           * cos(k x + phi);   V_I = prod_j v_j(x_j)
+ *                  (evolve and energy also take eps V_I as an explicit array
+ *                  over the grid, which replaces this factor form)
  *   [40..42]       W_xy, W_xz, W_yz: constant off-diagonal entries of the
  *                  squared-frequency matrix W(t) of a coupled trap
  *                  V_HO = (mu/2) x^T W(t) x, W_jj = omega_j(t)^2 (the general
@@ -715,8 +717,10 @@ static long axis_index(const grid_t *G, long idx, int axis)
     return (idx / s) % G->n[axis];
 }
 
+/* vi_in: eps V_I at every point (row-major, x fastest), or NULL for the
+ * separable factor form of the parameter block. */
 static int grid_init(grid_t *G, int ndim, const int *n, const double *lo, const double *hi,
-                     const double *par)
+                     const double *par, const double *vi_in)
 {
     memset(G, 0, sizeof(*G));
     if (ndim < 1 || ndim > 3) return ORC_EINVAL;
@@ -755,7 +759,7 @@ static int grid_init(grid_t *G, int ndim, const int *n, const double *lo, const 
             long i = axis_index(G, idx, j);
             v *= vfactor(par, j, G->lo[j] + i * G->dx[j]);
         }
-        G->vi[idx] = eps * v;
+        G->vi[idx] = vi_in ? vi_in[idx] : eps * v;
     }
     return ORC_OK;
 }
@@ -961,11 +965,11 @@ static int step_once(const grid_t *G, double *u, int m, const double *a, const d
  * complex (re, im) in row-major order with x fastest. */
 int orc_evolve(int ndim, const int *n, const double *lo, const double *hi, const double *par,
                int m, const double *a, const double *b, int rule, int q, double dt, double t0,
-               long nsteps, double *psi)
+               long nsteps, const double *vi, double *psi)
 {
     if (m < 1 || nsteps < 0) return ORC_EINVAL;
     grid_t G;
-    int rc = grid_init(&G, ndim, n, lo, hi, par);
+    int rc = grid_init(&G, ndim, n, lo, hi, par, vi);
     if (rc) { grid_free(&G); return rc; }
     for (long s = 0; s < nsteps && rc == ORC_OK; ++s)
         rc = step_once(&G, psi, m, a, b, rule, q, dt, t0 + (double)s * dt);
@@ -1012,10 +1016,10 @@ int orc_norm(int ndim, const int *n, const double *lo, const double *hi, const d
  *   V = sum_j mu omega_j(t)^2 x_j^2 / 2 + eps V_I(x).
  * out[0..3] = total, kinetic, potential, interaction. */
 int orc_energy(int ndim, const int *n, const double *lo, const double *hi, const double *par,
-               double t, const double *psi, double *out)
+               double t, const double *vi, const double *psi, double *out)
 {
     grid_t G;
-    int rc = grid_init(&G, ndim, n, lo, hi, par);
+    int rc = grid_init(&G, ndim, n, lo, hi, par, vi);
     if (rc) { grid_free(&G); return rc; }
     double cell = 1.0;
     for (int j = 0; j < ndim; ++j) cell *= G.dx[j];
@@ -1065,7 +1069,7 @@ int orc_drift(int ndim, const int *n, const double *lo, const double *hi, const 
     par[0] = 1.0;
     for (int j = 0; j < 3; ++j) par[18 + 6 * j] = 1.0;
     grid_t G;
-    int rc = grid_init(&G, ndim, n, lo, hi, par);
+    int rc = grid_init(&G, ndim, n, lo, hi, par, NULL);
     if (rc == ORC_OK) rc = apply_D(&G, psi, g);
     grid_free(&G);
     return rc;

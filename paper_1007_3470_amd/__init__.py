@@ -28,7 +28,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "si
           -7: "non-finite coefficient", -8: "no gfx950 device"}
 SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", "hfgpe_evolve",
            "hfgpe_norm", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
-           "hfgpe_stage_coeffs_coupled",
+           "hfgpe_stage_coeffs_coupled", "hfgpe_set_potential",
            "hfgpe_scheme_preset",
            "hfgpe_device_status", "hfgpe_profile", "hfgpe_autotune", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
 
@@ -96,6 +96,7 @@ def load() -> ctypes.CDLL:
     lib.hfgpe_instance_offsets.argtypes = [vp, i64p]
     lib.hfgpe_evolve.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64]
     lib.hfgpe_norm.argtypes = [vp, vp, dp]
+    lib.hfgpe_set_potential.argtypes = [vp, vp]
     lib.hfgpe_energy.argtypes = [vp, vp, ctypes.c_double, dp]
     lib.hfgpe_stage_coeffs.argtypes = [vp, ctypes.c_int, ctypes.c_double, dp]
     lib.hfgpe_stage_coeffs_params.argtypes = [ctypes.POINTER(Params), ctypes.c_int,
@@ -253,6 +254,28 @@ class Plan:
     def evolve(self, buf, t0: float, nsteps: int) -> None:
         _check(self.lib.hfgpe_evolve(self.handle, self._ptr(buf), float(t0), int(nsteps)),
                "hfgpe_evolve")
+
+    def set_potential(self, vi) -> None:
+        """Use a device tensor of eps V_I per point (float64, the state's packed
+        layout) instead of the factor form; None restores it.  The tensor is
+        kept referenced by the plan."""
+        if vi is None:
+            self._vi = None
+            _check(self.lib.hfgpe_set_potential(self.handle, None), "hfgpe_set_potential")
+            return
+        import torch
+        assert vi.is_cuda and vi.dtype == torch.float64 and vi.is_contiguous()
+        assert vi.numel() >= self.offsets[-1]
+        self._vi = vi
+        _check(self.lib.hfgpe_set_potential(self.handle, ctypes.c_void_p(vi.data_ptr())),
+               "hfgpe_set_potential")
+
+    def pack_real(self, arrays):
+        """Host real arrays (one per instance) -> packed float64 device tensor."""
+        import torch
+        flat = np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in arrays])
+        assert flat.size == self.offsets[-1]
+        return torch.from_numpy(flat).to("cuda")
 
     def norm(self, buf) -> np.ndarray:
         out = (ctypes.c_double * max(1, self.n_inst))()

@@ -93,6 +93,9 @@ struct hfgpe_plan {
     int graph_rec_steps = -1;
     int graph_grid = -1;
     void *graph_psi = nullptr;
+    const double *graph_vi = nullptr;
+    // caller's eps V_I per point (hfgpe_set_potential), or null
+    const double *d_vi = nullptr;
     int twlog = 0;
     double *d_vtab = nullptr;  // d-D: V_I factor per axis on its grid
     int vtab_stride = 0;
@@ -431,6 +434,7 @@ static int nd_step(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const in
             L.recx = P->d_recx;
             L.recx_open = P->d_recx_open;
             L.kind = pkind[pp];
+            L.vi = P->d_vi;
             L.vtab = P->d_vtab;
             L.vtab_stride = P->vtab_stride;
             L.cistab = P->d_cistab;
@@ -470,7 +474,8 @@ static int nd_step(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const in
 // kGraphSteps steps followed by the base advance.
 static int nd_graph_ready(hfgpe_plan *P, void *d_psi, int rec_steps)
 {
-    if (P->graph_exec && P->graph_rec_steps == rec_steps && P->graph_grid == P->nd_grid && P->graph_psi == d_psi)
+    if (P->graph_exec && P->graph_rec_steps == rec_steps && P->graph_grid == P->nd_grid && P->graph_psi == d_psi &&
+        P->graph_vi == P->d_vi)
         return HFGPE_OK;
     if (P->graph_exec) {
         (void)hipGraphExecDestroy(P->graph_exec);
@@ -501,6 +506,7 @@ static int nd_graph_ready(hfgpe_plan *P, void *d_psi, int rec_steps)
     P->graph_rec_steps = rec_steps;
     P->graph_grid = P->nd_grid;
     P->graph_psi = d_psi;
+    P->graph_vi = P->d_vi;
     return HFGPE_OK;
 }
 
@@ -866,6 +872,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
                 L.rec = P->d_rec;
                 L.rec_open = P->d_rec_open;
                 L.cistab = P->d_cistab;
+                L.vi = P->d_vi;
                 L.psi = d_psi;
                 L.m = m;
                 L.K = kk;
@@ -913,6 +920,7 @@ static int run_reduce(hfgpe_plan *P, const void *d_psi, int energy, double t, st
     R.c64 = P->dtype == HFGPE_C64;
     R.energy = energy;
     R.t = t;
+    R.vi = P->d_vi;
     R.part = P->d_part;
     R.stream = P->stream;
     HIP_TRY(launch_reduce_pointwise(R));
@@ -994,6 +1002,13 @@ int hfgpe_energy(hfgpe_plan *P, const void *d_psi, double t, double *h_out)
         h_out[4 * k + 2] = ep;
         h_out[4 * k + 3] = ei;
     }
+    return HFGPE_OK;
+}
+
+int hfgpe_set_potential(hfgpe_plan *P, const double *d_vi)
+{
+    if (!P) return HFGPE_E_INVALID_ARG;
+    P->d_vi = d_vi;
     return HFGPE_OK;
 }
 

@@ -52,7 +52,7 @@ template <typename Store, int P, int MAXS, int MODE, int TPB, int KIND>
 __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     const InstDev *__restrict__ insts, int n_inst, const Rec *__restrict__ rec,
     const Rec *__restrict__ rec_open, const RecX *__restrict__ recx, const RecX *__restrict__ recx_open,
-    const double *__restrict__ vtab, int vtab_stride,
+    const double *__restrict__ vi, const double *__restrict__ vtab, int vtab_stride,
     const double2 *__restrict__ cistab, const double2 *__restrict__ twtab, int twlog,
     Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step_off,
     const int *__restrict__ step_base)
@@ -207,7 +207,10 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
                 const int i = tl + c * T;
                 const double x = loa + (double)i * dxa;
                 double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
-                double th = fma(x, fma(chia, 0.5 * x, lin), fma(wv0, va[i], fma(q.s, a2, th0)));
+                // eps V_I: the caller's value at the point, or the factor form
+                const double rest = fma(q.s, a2, th0);
+                const double bv = vi ? fma(q.w, vi[I.offset + base + i * estr], rest) : fma(wv0, va[i], rest);
+                double th = fma(x, fma(chia, 0.5 * x, lin), bv);
                 u[c] = cmul(u[c], cis_neg_tab(th, ctab));
                 // keep the scheduler from interleaving all P phase evaluations
                 // (register pressure); pairs still overlap
@@ -388,7 +391,7 @@ static hipError_t launch_pass_tpb(const LaunchND &L)
     int lG = nd_group_log(L.n, L.axis, TPB);
     int threads = 1 << (lG + sh.logn[L.axis] - Log2<P>::value);
     hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE, TPB, KIND>), dim3(L.grid), dim3(threads), 0, L.stream,
-                       L.insts, L.n_inst, L.rec, L.rec_open, L.recx, L.recx_open, L.vtab, L.vtab_stride, L.cistab,
+                       L.insts, L.n_inst, L.rec, L.rec_open, L.recx, L.recx_open, L.vi, L.vtab, L.vtab_stride, L.cistab,
                        L.twtab, L.twlog, (Store *)L.psi, sh, L.axis, lG, L.stage, L.m, L.rec_steps, L.step,
                        L.step_base);
     return hipGetLastError();

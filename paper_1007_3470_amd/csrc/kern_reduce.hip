@@ -29,7 +29,8 @@ struct Ksum {
 template <typename Store>
 __global__ __launch_bounds__(256) void reduce_kernel(const InstDev *__restrict__ insts, int nblk,
                                                      const Store *__restrict__ psi, int energy,
-                                                     double t, double *__restrict__ part)
+                                                     double t, const double *__restrict__ vi,
+                                                     double *__restrict__ part)
 {
     __shared__ double sh[3][256];
     const int inst = blockIdx.x / nblk;
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const InstDev *__restrict__
             }
             if (I.coupled)  // off-diagonal part of (mu/2) x^T W x
                 V += I.mu * (I.wx[0] * xs[0] * xs[1] + I.wx[1] * xs[0] * xs[2] + I.wx[2] * xs[1] * xs[2]);
-            V += I.eps * VI;
+            V += vi ? vi[I.offset + idx] : I.eps * VI;
             b.add(V * a2);
             c.add(0.5 * sig * a2 * a2);
         }
@@ -84,10 +85,10 @@ hipError_t launch_reduce_pointwise(const LaunchReduce &L)
     dim3 grid((unsigned)(L.n_inst * L.nblk));
     if (L.c64)
         hipLaunchKernelGGL(reduce_kernel<float2>, grid, dim3(256), 0, L.stream, L.insts, L.nblk,
-                           (const float2 *)L.psi, L.energy, L.t, L.part);
+                           (const float2 *)L.psi, L.energy, L.t, L.vi, L.part);
     else
         hipLaunchKernelGGL(reduce_kernel<double2>, grid, dim3(256), 0, L.stream, L.insts, L.nblk,
-                           (const double2 *)L.psi, L.energy, L.t, L.part);
+                           (const double2 *)L.psi, L.energy, L.t, L.vi, L.part);
     return hipGetLastError();
 }
 
