@@ -194,6 +194,23 @@ int hfgpe_instance_offsets(const hfgpe_plan *plan, int64_t *off);
  * nsteps = 0 does nothing. */
 int hfgpe_evolve(hfgpe_plan *plan, void *d_psi, double t0, int64_t nsteps);
 
+/* User-defined harmonic-oscillator stages (the exact flow for an omega(t)
+ * known only to the caller, e.g. from a host callback or a numerically
+ * integrated fundamental matrix, or a table of coefficients): fn returns, for
+ * instance inst and axis, the K(f) D(g) K(e) factorisation of the HO flow of
+ * that axis over [t0, t0 + tau] (e acts first; K(c) = exp(-i c x^2/2),
+ * D(g) = exp(-i g k^2/2), Sec. 2.2) in fge[0..2] = f, g, e, and 0; any other
+ * return value makes hfgpe_evolve fail with INVALID_ARG.  The library merges
+ * the chirps and the B weights as for its own rules; the plan's HO rule is
+ * then ignored (and no harmonic term enters B).  fn is called on the host, from
+ * the thread calling hfgpe_evolve, for every instance, step, stage and axis of
+ * each chunk of steps, before the chunk's records are copied (async, on the
+ * plan's stream) to the device.  fn = NULL restores the plan's rule.
+ * Diagonal traps only (INVALID_ARG for coupled plans). */
+typedef int (*hfgpe_stage_fn)(void *user, int inst, int axis, double t0, double tau, double mu,
+                              double *fge);
+int hfgpe_set_stage_callback(hfgpe_plan *plan, hfgpe_stage_fn fn, void *user);
+
 /* Perturbation as a device array (Sec. 1: V_I is any potential; the B flow of
  * Lemma 1 is pointwise): d_vi holds eps V_I(x) in FP64 at every grid point of
  * every instance, in the packed layout of the state (hfgpe_instance_offsets),

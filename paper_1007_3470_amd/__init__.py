@@ -28,7 +28,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "si
           -7: "non-finite coefficient", -8: "no gfx950 device"}
 SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", "hfgpe_evolve",
            "hfgpe_norm", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
-           "hfgpe_stage_coeffs_coupled", "hfgpe_set_potential",
+           "hfgpe_stage_coeffs_coupled", "hfgpe_set_potential", "hfgpe_set_stage_callback",
            "hfgpe_scheme_preset",
            "hfgpe_device_status", "hfgpe_profile", "hfgpe_autotune", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
 
@@ -77,6 +77,10 @@ class Options(ctypes.Structure):
                 ("nd_workgroups", ctypes.c_int)]
 
 
+# int fn(void *user, int inst, int axis, double t0, double tau, double mu, double *fge)
+STAGE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                            ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double))
+
 _lib = None
 
 
@@ -97,6 +101,7 @@ def load() -> ctypes.CDLL:
     lib.hfgpe_evolve.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64]
     lib.hfgpe_norm.argtypes = [vp, vp, dp]
     lib.hfgpe_set_potential.argtypes = [vp, vp]
+    lib.hfgpe_set_stage_callback.argtypes = [vp, STAGE_FN, vp]
     lib.hfgpe_energy.argtypes = [vp, vp, ctypes.c_double, dp]
     lib.hfgpe_stage_coeffs.argtypes = [vp, ctypes.c_int, ctypes.c_double, dp]
     lib.hfgpe_stage_coeffs_params.argtypes = [ctypes.POINTER(Params), ctypes.c_int,
@@ -254,6 +259,28 @@ class Plan:
     def evolve(self, buf, t0: float, nsteps: int) -> None:
         _check(self.lib.hfgpe_evolve(self.handle, self._ptr(buf), float(t0), int(nsteps)),
                "hfgpe_evolve")
+
+    def set_stage_callback(self, fn) -> None:
+        """Harmonic-oscillator stages from a Python function
+        fn(inst, axis, t0, tau, mu) -> (f, g, e), the K(f) D(g) K(e) factors of
+        that axis's flow over [t0, t0 + tau]; None restores the plan's rule."""
+        if fn is None:
+            self._stage_cb = None
+            _check(self.lib.hfgpe_set_stage_callback(self.handle, STAGE_FN(), None),
+                   "hfgpe_set_stage_callback")
+            return
+
+        def tramp(user, inst, axis, t0, tau, mu, out):
+            try:
+                f, g, e = fn(inst, axis, t0, tau, mu)
+                out[0], out[1], out[2] = float(f), float(g), float(e)
+                return 0
+            except Exception:  # noqa: BLE001 - reported to the library as a failed stage
+                return 1
+
+        self._stage_cb = STAGE_FN(tramp)
+        _check(self.lib.hfgpe_set_stage_callback(self.handle, self._stage_cb, None),
+               "hfgpe_set_stage_callback")
 
     def set_potential(self, vi) -> None:
         """Use a device tensor of eps V_I per point (float64, the state's packed

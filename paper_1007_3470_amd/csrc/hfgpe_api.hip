@@ -96,6 +96,14 @@ struct hfgpe_plan {
     const double *graph_vi = nullptr;
     // caller's eps V_I per point (hfgpe_set_potential), or null
     const double *d_vi = nullptr;
+    // caller's HO stages (hfgpe_set_stage_callback): records built on the
+    // host in pinned staging memory, copied per chunk
+    hfgpe_stage_fn stage_fn = nullptr;
+    void *stage_user = nullptr;
+    Rec *h_stage = nullptr;
+    int cb_steps_cap = 0;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_ev_pending = false;
     int twlog = 0;
     double *d_vtab = nullptr;  // d-D: V_I factor per axis on its grid
     int vtab_stride = 0;
@@ -116,6 +124,9 @@ struct hfgpe_plan {
         if (d_rec) (void)hipFree(d_rec);
         if (d_rec_open) (void)hipFree(d_rec_open);
         if (d_recx) (void)hipFree(d_recx);
+        if (stage_ev_pending) (void)hipEventSynchronize(stage_ev);
+        if (h_stage) (void)hipHostFree(h_stage);
+        if (stage_ev) (void)hipEventDestroy(stage_ev);
         if (d_recx_open) (void)hipFree(d_recx_open);
         if (d_part) (void)hipFree(d_part);
         if (d_kin) (void)hipFree(d_kin);
@@ -388,6 +399,76 @@ void build_groups_1d(hfgpe_plan &P, bool plain)
 }
 
 }  // namespace
+
+// Records of a chunk from the caller's stage function: the merging of the
+// coefficient kernel (chi = f_i + e_{i+1}; FSAL across steps; B weights and
+// sigma from the plan), evaluated on the host into the staging buffer.
+static int host_stage_records(hfgpe_plan *P, double t0, int64_t s0, int k, int64_t nsteps)
+{
+    const SchemeDev &S = P->scheme;
+    const int m = S.m;
+    const double dt = P->dt;
+    Rec *rec_open = P->h_stage + (size_t)P->n_inst * k * m;
+    for (int inst = 0; inst < P->n_inst; ++inst) {
+        const InstDev &I = P->insts[inst];
+        const int nd = I.ndim;
+        auto stage = [&](double tau0, int i, double *fge) -> int {
+            for (int j = 0; j < nd; ++j) {
+                int rc = P->stage_fn(P->stage_user, inst, j, tau0, dt * S.a[i], I.mu, fge + 3 * j);
+                if (rc != 0) return HFGPE_E_INVALID_ARG;
+                if (!std::isfinite(fge[3 * j]) || !std::isfinite(fge[3 * j + 1]) || !std::isfinite(fge[3 * j + 2]))
+                    return HFGPE_E_NONFINITE;
+            }
+            return HFGPE_OK;
+        };
+        for (int s = 0; s < k; ++s) {
+            const int64_t n = s0 + s;
+            const double tn = t0 + (double)n * dt, tn1 = t0 + (double)(n + 1) * dt;
+            const bool last = (n == nsteps - 1);
+            double cur[9], nxt[9];
+            int rc = stage(tn, 0, cur);
+            if (rc) return rc;
+            if (n == 0) {
+                Rec o;
+                for (int j = 0; j < 3; ++j) {
+                    o.g[j] = 0.0;
+                    o.chi[j] = (j < nd) ? cur[3 * j + 2] : 0.0;
+                }
+                o.w = dt * S.b[0];
+                o.s = o.w * tf_value(I.sig, tn);
+                rec_open[inst] = o;
+            }
+            Rec *out = P->h_stage + ((size_t)inst * k + s) * m;
+            for (int i = 0; i < m; ++i) {
+                Rec r;
+                for (int j = 0; j < 3; ++j) { r.g[j] = 0.0; r.chi[j] = 0.0; }
+                for (int j = 0; j < nd; ++j) r.g[j] = cur[3 * j + 1];
+                double tau_next;
+                if (i < m - 1) {
+                    tau_next = tn + dt * S.cum[i + 1];
+                    rc = stage(tau_next, i + 1, nxt);
+                    if (rc) return rc;
+                    for (int j = 0; j < nd; ++j) r.chi[j] = cur[3 * j] + nxt[3 * j + 2];
+                    r.w = dt * S.b[i + 1];
+                } else if (!last) {
+                    tau_next = tn1;
+                    rc = stage(tn1, 0, nxt);
+                    if (rc) return rc;
+                    for (int j = 0; j < nd; ++j) r.chi[j] = cur[3 * j] + nxt[3 * j + 2];
+                    r.w = dt * (S.b[m] + S.b[0]);
+                } else {
+                    tau_next = tn1;
+                    for (int j = 0; j < nd; ++j) r.chi[j] = cur[3 * j];
+                    r.w = dt * S.b[m];
+                }
+                r.s = r.w * tf_value(I.sig, tau_next);
+                out[i] = r;
+                if (i < m - 1) std::memcpy(cur, nxt, sizeof(cur));
+            }
+        }
+    }
+    return HFGPE_OK;
+}
 
 static int take_events(hfgpe_plan *P, std::pair<hipEvent_t, hipEvent_t> &out)
 {
@@ -809,7 +890,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
     if (nsteps == 0 || P->n_inst == 0) return HFGPE_OK;
     if (!d_psi) return HFGPE_E_INVALID_ARG;
     const int m = P->scheme.m;
-    int chunk = (int)std::min<int64_t>(nsteps, P->rec_steps_cap);
+    int chunk = (int)std::min<int64_t>(nsteps, P->stage_fn ? P->cb_steps_cap : P->rec_steps_cap);
     const bool plain = P->opts.plain != 0;
     int per_launch = plain ? 1 : (P->opts.steps_per_launch > 0 ? P->opts.steps_per_launch : chunk);
     for (int64_t s0 = 0; s0 < nsteps; s0 += chunk) {
@@ -829,16 +910,31 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
         C.nsteps_total = nsteps;
         C.err = P->d_err;
         C.stream = P->stream;
-        std::pair<hipEvent_t, hipEvent_t> ec{};
-        if (P->opts.profile) {
-            int rc = take_events(P, ec);
+        if (P->stage_fn) {
+            // the staging buffer is reused: wait for the previous chunk's copy
+            if (P->stage_ev_pending) HIP_TRY(hipEventSynchronize(P->stage_ev));
+            P->stage_ev_pending = false;
+            int rc = host_stage_records(P, t0, s0, k, nsteps);
             if (rc) return rc;
-            HIP_TRY(hipEventRecord(ec.first, P->stream));
-        }
-        HIP_TRY(launch_coeff(C));
-        if (P->opts.profile) {
-            HIP_TRY(hipEventRecord(ec.second, P->stream));
-            P->ev_coeff.push_back(ec);
+            const size_t nrec = (size_t)P->n_inst * k * m;
+            HIP_TRY(hipMemcpyAsync(P->d_rec, P->h_stage, sizeof(Rec) * nrec, hipMemcpyHostToDevice, P->stream));
+            if (s0 == 0)
+                HIP_TRY(hipMemcpyAsync(P->d_rec_open, P->h_stage + nrec, sizeof(Rec) * P->n_inst,
+                                       hipMemcpyHostToDevice, P->stream));
+            HIP_TRY(hipEventRecord(P->stage_ev, P->stream));
+            P->stage_ev_pending = true;
+        } else {
+            std::pair<hipEvent_t, hipEvent_t> ec{};
+            if (P->opts.profile) {
+                int rc = take_events(P, ec);
+                if (rc) return rc;
+                HIP_TRY(hipEventRecord(ec.first, P->stream));
+            }
+            HIP_TRY(launch_coeff(C));
+            if (P->opts.profile) {
+                HIP_TRY(hipEventRecord(ec.second, P->stream));
+                P->ev_coeff.push_back(ec);
+            }
         }
         if (P->ndim > 1) {
             int st = 0;
@@ -1002,6 +1098,37 @@ int hfgpe_energy(hfgpe_plan *P, const void *d_psi, double t, double *h_out)
         h_out[4 * k + 2] = ep;
         h_out[4 * k + 3] = ei;
     }
+    return HFGPE_OK;
+}
+
+int hfgpe_set_stage_callback(hfgpe_plan *P, hfgpe_stage_fn fn, void *user)
+{
+    if (!P || P->coupled) return HFGPE_E_INVALID_ARG;
+    if (fn && P->n_inst > 0 && !P->h_stage) {
+        // pinned staging for up to 64 MB of records per chunk
+        const size_t per_step = (size_t)P->n_inst * P->scheme.m * sizeof(Rec);
+        P->cb_steps_cap = (int)std::max<size_t>(1, std::min<size_t>(((size_t)64 << 20) / per_step,
+                                                                    (size_t)P->rec_steps_cap));
+        const size_t bytes = per_step * P->cb_steps_cap + sizeof(Rec) * P->n_inst;
+        hipError_t e = hipHostMalloc((void **)&P->h_stage, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            g_last_hip_error = (int)e;
+            P->h_stage = nullptr;
+            return HFGPE_E_ALLOC;
+        }
+        e = hipEventCreateWithFlags(&P->stage_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            g_last_hip_error = (int)e;
+            return HFGPE_E_HIP;
+        }
+    }
+    if (!fn && P->stage_ev_pending) {
+        // the staging buffer may still be read by an earlier copy
+        HIP_TRY(hipEventSynchronize(P->stage_ev));
+        P->stage_ev_pending = false;
+    }
+    P->stage_fn = fn;
+    P->stage_user = user;
     return HFGPE_OK;
 }
 

@@ -1,0 +1,129 @@
+"""User-defined harmonic-oscillator stages (hfgpe_set_stage_callback): the
+callbacks below write Lemma 2 and Theorem 2 out in Python (independently of
+both the library and the oracle), and the results are compared with the
+oracle's own rules."""
+import math
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1007_3470_amd as p
+    p.load()
+    return p
+
+
+def omega_of(inst, j, t):
+    v0, a, f, ph = inst.omega[j][:4]
+    return v0 * (1.0 + a * math.sin(f * t + ph))
+
+
+def lemma2(instances):
+    """Constant omega: f = e = mu w tan(w tau / 2), g = sin(w tau) / (mu w)."""
+    def fn(inst, axis, t0, tau, mu):
+        w = instances[inst].omega[axis][0]
+        f = mu * w * math.tan(0.5 * w * tau)
+        return f, math.sin(w * tau) / (mu * w), f
+    return fn
+
+
+def theorem2(instances):
+    """Commutator-free product (Eq. CommutatorFree) factored by Theorem 2:
+    omega_L^2, omega_R^2 from the two Gauss nodes; the omega_R factor acts first."""
+    r3 = math.sqrt(3.0)
+    c1, c2 = 0.5 - r3 / 6.0, 0.5 + r3 / 6.0
+    al = 0.5 - 1.0 / r3
+    be = 1.0 - al
+
+    def fn(inst, axis, t0, tau, mu):
+        I = instances[inst]
+        w1, w2 = omega_of(I, axis, t0 + c1 * tau), omega_of(I, axis, t0 + c2 * tau)
+        wL = math.sqrt(al * w1 * w1 + be * w2 * w2)
+        wR = math.sqrt(be * w1 * w1 + al * w2 * w2)
+        yL, yR = 0.5 * wL * tau, 0.5 * wR * tau
+        g = math.sin(yL) * math.cos(yR) / wL + math.cos(yL) * math.sin(yR) / wR
+        one_m = 2 * math.sin(0.5 * yL) ** 2 + math.cos(yL) * 2 * math.sin(0.5 * yR) ** 2
+        f = (one_m + wL / wR * math.sin(yL) * math.sin(yR)) / g
+        e = (one_m + wR / wL * math.sin(yL) * math.sin(yR)) / g
+        return mu * f, g / mu, mu * e
+    return fn
+
+
+def run(pkg, w, dtype, fn, nsteps=None, **kw):
+    import torch
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, **kw)
+    if fn is not None:
+        plan.set_stage_callback(fn)
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, w.t0, w.nsteps if nsteps is None else nsteps)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    return plan, plan.unpack(buf)
+
+
+def test_callback_lemma2_matches_exact_rule(pkg):
+    w = W.coherent_1d(n=512, lo=-12.0, hi=12.0, x0=0.8, dt=0.05, nsteps=200, omega=1.3, mu=2.0)
+    _, got = run(pkg, w, "c128", lemma2(w.instances))
+    ref = oracle.evolve(w.instances[0], w.psi0[0], "leapfrog", "exact_const", w.dt, 0.0, w.nsteps)
+    assert W.rel_l2(got[0], ref) < 1e-11
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_callback_theorem2_matches_cf4_2d(pkg, dtype):
+    w = W.gpe_2d(n=64, n_inst=2, nsteps=15, scheme="ni4_82")
+    _, got = run(pkg, w, dtype, theorem2(w.instances))
+    for k, inst in enumerate(w.instances):
+        ref = oracle.evolve(inst, w.psi0[k], w.scheme, "cf4", w.dt, w.t0, w.nsteps)
+        assert W.rel_l2(got[k], ref) < (1e-11 if dtype == "c128" else 5e-5)
+
+
+def test_callback_multi_chunk_batch(pkg):
+    """4096 instances: the 64 MB staging holds 256 steps, so 600 steps take three
+    chunks; compared with the library's own CF4 rule and the oracle."""
+    w = W.batch_1d(nsteps=600)
+    _, cb = run(pkg, w, "c128", theorem2(w.instances))
+    _, rule = run(pkg, w, "c128", None)
+    worst = max(W.rel_l2(a, b) for a, b in zip(cb, rule))
+    print("callback vs built-in cf4, 4096 instances x 600 steps: %.3e" % worst, flush=True)
+    assert worst < 1e-12
+    for k in (0, 1777, 4095):
+        ref = oracle.evolve(w.instances[k], w.psi0[k], w.scheme, "cf4", w.dt, 0.0, w.nsteps)
+        assert W.rel_l2(cb[k], ref) < 1e-11
+
+
+def test_callback_failure_and_reset(pkg):
+    import torch
+    w = W.gpe_2d(n=32, n_inst=1, nsteps=4)
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", w.dt)
+
+    def bad(inst, axis, t0, tau, mu):
+        raise ValueError("no coefficients")
+    plan.set_stage_callback(bad)
+    buf = plan.pack(w.psi0)
+    with pytest.raises(pkg.HfgpeError) as e:
+        plan.evolve(buf, 0.0, 4)
+    assert e.value.code == -1
+    plan.set_stage_callback(None)
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, 0.0, 4)
+    torch.cuda.synchronize()
+    _, ref = run(pkg, w, "c128", None)
+    assert np.array_equal(plan.unpack(buf)[0], ref[0])
+
+
+def test_callback_rejected_for_coupled_plan(pkg):
+    w = W.coupled_2d(n=16, n_inst=1, nsteps=1)
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", w.dt)
+    with pytest.raises(pkg.HfgpeError) as e:
+        plan.set_stage_callback(lemma2(w.instances))
+    assert e.value.code == -1
