@@ -163,6 +163,10 @@ typedef struct {
     int profile;           /* 1 = bracket every step-kernel launch with HIP
                               events on the plan's stream (hfgpe_profile) */
     int nd_workgroups;     /* d-D: persistent workgroups per axis pass (0 = auto) */
+    int nd_generic;        /* d-D: 1 = every axis pass runs the runtime-shaped
+                              FFT (by default separable passes along axes of
+                              128 .. 1024 points run fixed-shape instances;
+                              both give the same bits) */
 } hfgpe_options;
 
 typedef struct hfgpe_plan hfgpe_plan;

@@ -198,7 +198,10 @@ struct FftFix8 {
     int woff[S > 2 ? S - 2 : 1];  // pass s write base, s = 1 .. S-2
     double2 tw[S - 1][3];         // w^1, w^2, w^4 of passes 1 .. S-1
 
-    __device__ __forceinline__ void init(int tl, int slot, double2 *lds_)
+    // twtab (optional): exp(-2 pi i q / 2^twlog) for q < 2^twlog, twlog >= LOGN;
+    // without it the twiddles are evaluated with sincospi
+    __device__ __forceinline__ void init(int tl, int slot, double2 *lds_, const double2 *__restrict__ twtab = nullptr,
+                                         int twlog = 0)
     {
         lds = lds_;
         const int row = slot * ROW;
@@ -218,9 +221,13 @@ struct FftFix8 {
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int e = ((1 << q) * k) << slog;
-                double sn, cs;
-                sincospi(-2.0 * (double)e * invN, &sn, &cs);
-                tw[s - 1][q] = make_double2(cs, sn);
+                if (twtab) {
+                    tw[s - 1][q] = twtab[e << (twlog - LOGN)];
+                } else {
+                    double sn, cs;
+                    sincospi(-2.0 * (double)e * invN, &sn, &cs);
+                    tw[s - 1][q] = make_double2(cs, sn);
+                }
             }
         }
     }
@@ -256,6 +263,80 @@ struct FftFix8 {
                 const int L = 1 << (R0LOG + LOGP * (s - 1));
 #pragma unroll
                 for (int rp = 0; rp < P; ++rp) lds[woff[s - 1] + rp * L + ((rp * L) >> 3)] = u[rp];
+            }
+        }
+    }
+};
+
+// Fixed-shape radix-8 FFT of the strided d-D axis passes: the G pencils of a
+// workgroup are interleaved in LDS (point idx of pencil `slot` at idx * G +
+// slot, no padding), a pencil's N = 2^LOGN points are split over T = N/8
+// threads, and the passes and twiddles are those of Fft1D.  As in FftFix8 every
+// LDS address is a per-thread base plus a compile-time constant.
+template <int LOGN, int G>
+struct FftFixS8 {
+    static constexpr int P = 8, LOGP = 3;
+    static constexpr int N = 1 << LOGN;
+    static constexpr int LOGT = LOGN - LOGP;
+    static constexpr int T = 1 << LOGT;
+    static constexpr int S = (LOGN + LOGP - 1) / LOGP;
+    static constexpr int R0LOG = LOGN - LOGP * (S - 1);
+    static constexpr int R0 = 1 << R0LOG;
+    static_assert(S >= 2 && G >= 1, "fixed-shape strided FFT: N >= 16");
+
+    double2 *lds;
+    int roff;                     // tl G + slot: point tl of the pencil
+    int w0off;                    // tl R0 G + slot: pass 0 write base
+    int woff[S > 2 ? S - 2 : 1];  // pass s write base, s = 1 .. S-2
+    double2 tw[S - 1][3];         // w^1, w^2, w^4 of passes 1 .. S-1
+
+    __device__ __forceinline__ void init(int tl, int slot, double2 *lds_, const double2 *__restrict__ twtab,
+                                         int twlog)
+    {
+        lds = lds_;
+        roff = tl * G + slot;
+        w0off = tl * R0 * G + slot;
+#pragma unroll
+        for (int s = 1; s < S; ++s) {
+            const int logL = R0LOG + LOGP * (s - 1);
+            const int k = tl & ((1 << logL) - 1);
+            if (s < S - 1) woff[s - 1] = ((tl - k) * P + k) * G + slot;
+            const int slog = LOGN - logL - LOGP;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) tw[s - 1][q] = twtab[(((1 << q) * k) << slog) << (twlog - LOGN)];
+        }
+    }
+
+    template <int SGN>
+    __device__ __forceinline__ void run(double2 *u)
+    {
+        constexpr int NB = P / R0;
+        constexpr int BSTR = T * R0 * G;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double2 v[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[r] = u[b + r * NB];
+            Dft<R0, SGN>::run(v);
+#pragma unroll
+            for (int rp = 0; rp < R0; ++rp) lds[w0off + b * BSTR + rp * G] = v[rp];
+        }
+#pragma unroll
+        for (int s = 1; s < S; ++s) {
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < P; ++c) u[c] = lds[roff + c * T * G];
+            __syncthreads();
+            const double2 w1 = tw[s - 1][0], w2 = tw[s - 1][1], w4 = tw[s - 1][2];
+            const double2 w3 = cmul(w1, w2);
+            const double2 w[7] = {w1, w2, w3, w4, cmul(w1, w4), cmul(w2, w4), cmul(w3, w4)};
+#pragma unroll
+            for (int r = 1; r < P; ++r) u[r] = (SGN < 0) ? cmul(u[r], w[r - 1]) : cmulc(u[r], w[r - 1]);
+            Dft<P, SGN>::run(u);
+            if (s < S - 1) {
+                const int L = 1 << (R0LOG + LOGP * (s - 1));
+#pragma unroll
+                for (int rp = 0; rp < P; ++rp) lds[woff[s - 1] + rp * L * G] = u[rp];
             }
         }
     }

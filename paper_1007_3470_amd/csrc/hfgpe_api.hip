@@ -534,6 +534,7 @@ static int nd_step(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const in
             L.apply_open = (first && i == 0 && pp == 0) ? 1 : 0;
             L.apply_close = (pp == np - 1) ? 1 : 0;
             L.grid = P->nd_grid;
+            L.generic = P->opts.nd_generic;
             L.stream = P->stream;
             std::pair<hipEvent_t, hipEvent_t> es{};
             const bool ev = profile && P->opts.profile;

@@ -1,273 +1,13 @@
-// kern_nd.hip -- 2-D / 3-D Hermite-Fourier axis passes for gfx950.
-//
-// The d-D drift D(g) = F^-1 exp(-i sum_j g_j k_j^2/2) F factors into one 1-D
-// drift per axis (the kinetic phase is separable and the per-axis transforms
-// commute), so a stage is d axis passes, each one HBM read and one HBM write
-// of the state:
-//   pass j: load pencils along axis j  [opening x-phase on the first pass of
-//           an evolve call]  ->  FFT_j  ->  exp(-i g_j k_j^2/2)/N_j  ->
-//           FFT_j^-1  [merged closing x-phase on the last axis]  ->  store.
-// Workgroups are persistent over groups of G pencils.  Along x the G pencils
-// are consecutive rows and a pencil's points are consecutive lanes; along a
-// strided axis the G pencils are G consecutive x positions, lanes run over
-// the pencils first (coalesced rows of G elements) and LDS is interleaved by
-// pencil.  The drift factors of a thread's P wavenumbers are computed once per
-// (workgroup, instance) and reused for every pencil it processes.
-//
-// A coupled trap (off-diagonal W) has a full quadratic drift k^T G k / 2 that
-// no longer factors per axis.  A stage is then 2d - 1 passes: forward
-// transforms along the axes 0 .. d-2, one pass along the last axis that
-// transforms forward, applies the whole drift (the other wavenumbers are fixed
-// along a pencil) and transforms back, then inverse transforms along
-// d-2 .. 0, the last of which applies the merged closing x-phase.  The x-phase
-// carries the off-diagonal chirp terms along a pencil as a linear term in the
-// pass coordinate.
+// kern_nd.hip -- 2-D / 3-D Hermite-Fourier axis passes for gfx950: launch
+// dispatch, the runtime-shaped pass instances and the kinetic-energy kernel.
+// The pass kernel itself and the d-D design are in nd_pass.hpp; separable
+// passes along axes of 128 .. 1024 points run the fixed-shape instances of
+// kern_nd_fix.hip.
 #include <hip/hip_runtime.h>
 
-#include "coeff.hpp"
-#include "devmath.hpp"
-#include "fft_lds.hpp"
-#include "kernels.hpp"
-#include "layout.hpp"
+#include "nd_pass.hpp"
 
 namespace hfgpe {
-
-constexpr int kThreadsND = 256;
-constexpr int kMaxAxisND = 1024;  // longest axis of a d-D plan
-
-struct NdShape {
-    int ndim;
-    int n[3];
-    int logn[3];
-};
-
-// KIND of pass: separable stage along one axis, or (coupled trap) forward
-// transform only, forward + whole drift + inverse, inverse transform only.
-enum { kPassSep = 0, kPassFwd = 1, kPassMid = 2, kPassInv = 3 };
-
-// MODE: 0 = no x-phase, 1 = closing x-phase at the end of the pass, 2 = opening
-// x-phase at its start (separate instantiations keep unused phase code out of
-// the register allocation).
-template <typename Store, int P, int MAXS, int MODE, int TPB, int KIND>
-__global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
-    const InstDev *__restrict__ insts, int n_inst, const Rec *__restrict__ rec,
-    const Rec *__restrict__ rec_open, const RecX *__restrict__ recx, const RecX *__restrict__ recx_open,
-    const double *__restrict__ vi, const double *__restrict__ vtab, int vtab_stride,
-    const double2 *__restrict__ cistab, const double2 *__restrict__ twtab, int twlog,
-    Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step_off,
-    const int *__restrict__ step_base)
-{
-    // step within the coefficient records: a fixed offset, plus a device-side
-    // base when the launch is replayed from a captured graph
-    const int step = step_off + (step_base ? *step_base : 0);
-    constexpr int LOGP = Log2<P>::value;
-    constexpr int LDS_ELEMS = TPB * P + ((TPB * P) >> kPadShift);
-    __shared__ double2 lds[LDS_ELEMS];
-    __shared__ CisTable ctab;
-    __shared__ double2 kfl[kMaxAxisND];  // drift factor of every wavenumber of the axis
-    load_cis_table(&ctab, cistab);
-    __syncthreads();
-
-    const int lnj = sh.logn[axis];
-    const int nj = 1 << lnj;
-    const int logT = lnj - LOGP;
-    const int T = 1 << logT;
-    int lstride = 0;
-    for (int j = 0; j < axis; ++j) lstride += sh.logn[j];
-    const int ltot = sh.logn[0] + sh.logn[1] + sh.logn[2];
-    const int64_t npencil = (int64_t)1 << (ltot - lnj);
-    // G = 2^lG pencils per group; the block has exactly G * T threads
-    const int G = 1 << lG;
-    const int64_t gpi = npencil >> lG;  // groups per instance
-    const int tid = threadIdx.x;
-    int slot, tl;
-    Fft1D<double2, P, MAXS> fft;
-    if (axis == 0) {
-        slot = tid >> logT;
-        tl = tid & (T - 1);
-        fft.istride = 1;
-        fft.pad = true;
-        fft.init(lnj, tl, lds + slot * (nj + (nj >> kPadShift)), twtab, twlog);
-    } else {
-        slot = tid & (G - 1);
-        tl = tid >> lG;
-        fft.istride = G;
-        fft.pad = false;
-        fft.init(lnj, tl, lds + slot, twtab, twlog);
-    }
-
-    const double invN = 1.0 / (double)nj;
-    int kf_inst = -1;
-
-    // each workgroup takes a contiguous range of groups (the drift factors change
-    // only when the instance does; neighbouring pencils share cache lines)
-    const int64_t total = (int64_t)n_inst * gpi;
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    const int64_t g_end = (blockIdx.x + 1) * per < total ? (blockIdx.x + 1) * per : total;
-    const int estr = (axis == 0) ? 1 : (1 << lstride);
-    // instance and first element of this thread's pencil in group gq (offsets
-    // within an instance fit in 32 bits)
-    auto locate = [&](int64_t gq, int &inst_q, int &base_q) {
-        inst_q = (int)(gq / gpi);
-        const int64_t g = gq - (int64_t)inst_q * gpi;
-        if (axis == 0) {
-            base_q = (int)(((g << lG) + slot) << lnj);
-        } else {
-            const int64_t ipo = ((int64_t)1 << lstride) >> lG;  // groups per outer index
-            const int inner = (int)((g % ipo) * G + slot);
-            const int outer = (int)(g / ipo);
-            base_q = outer * (nj << lstride) + inner;
-        }
-    };
-    // c64: the next group's points are loaded while the current one is
-    // transformed (the 16 extra registers fit; for c128 the 32 they would take
-    // cost more in spills than the hidden latency gains)
-    constexpr bool kPrefetch = sizeof(Store) == 8;
-    Store nxt[kPrefetch ? P : 1];
-    int inst_n = 0, base_n = 0;
-    const int64_t g_begin = blockIdx.x * per;
-    if constexpr (kPrefetch) {
-        if (g_begin < g_end) {
-            locate(g_begin, inst_n, base_n);
-            const Store *src = psi + insts[inst_n].offset + base_n;
-#pragma unroll
-            for (int c = 0; c < P; ++c) nxt[c] = src[(tl + c * T) * estr];
-        }
-    }
-    for (int64_t gg = g_begin; gg < g_end; ++gg) {
-        double2 u[P];
-        int inst, base;
-        if constexpr (kPrefetch) {
-            inst = inst_n;
-            base = base_n;
-#pragma unroll
-            for (int c = 0; c < P; ++c) u[c] = to_d2(nxt[c]);
-            if (gg + 1 < g_end) {
-                locate(gg + 1, inst_n, base_n);
-                const Store *src = psi + insts[inst_n].offset + base_n;
-#pragma unroll
-                for (int c = 0; c < P; ++c) nxt[c] = src[(tl + c * T) * estr];
-            }
-        } else {
-            locate(gg, inst, base);
-            const Store *src = psi + insts[inst].offset + base;
-#pragma unroll
-            for (int c = 0; c < P; ++c) u[c] = to_d2(src[(tl + c * T) * estr]);
-        }
-        const InstDev &I = insts[inst];
-        const Rec &r = rec[((size_t)inst * rec_steps + step) * m + stage];
-        if constexpr (KIND == kPassSep) {
-            if (inst != kf_inst) {  // uniform across the workgroup
-                const double gk = r.g[axis], ks = I.kscale[axis];
-                __syncthreads();
-                for (int q = threadIdx.x; q < nj; q += blockDim.x) {
-                    int sq = q - ((q >= (nj >> 1)) ? nj : 0);
-                    double k = ks * (double)sq;
-                    double2 f = cis_neg_tab(gk * (0.5 * k * k), ctab);
-                    kfl[q] = make_double2(f.x * invN, f.y * invN);
-                }
-                __syncthreads();
-                kf_inst = inst;
-            }
-        }
-        Store *u0 = psi + I.offset + base;
-
-        // merged x-phase: along a pencil only the pass axis's coordinate varies, so
-        // the other axes' chirp and V_I factors are formed once per pencil
-        auto xphase = [&](const Rec &q, const RecX *qx) {
-            double th0 = 0.0, v0 = I.eps, lin = 0.0;
-            double xo[3] = {0.0, 0.0, 0.0};  // coordinates of the pencil off the pass axis
-            int shift = 0;
-            for (int j = 0; j < sh.ndim; ++j) {
-                if (j != axis) {
-                    int i = (base >> shift) & (sh.n[j] - 1);
-                    double x = I.lo[j] + (double)i * I.dx[j];
-                    xo[j] = x;
-                    th0 = fma(q.chi[j], 0.5 * x * x, th0);
-                    v0 *= vtab[((size_t)inst * 3 + j) * vtab_stride + i];
-                }
-                shift += sh.logn[j];
-            }
-            if (qx) {  // off-diagonal chirp: sum_{i<j} C_ij x_i x_j
-#pragma unroll
-                for (int pr = 0; pr < 3; ++pr) {
-                    const int a = (pr == 2) ? 1 : 0, b = (pr == 0) ? 1 : 2;
-                    if (b >= sh.ndim) continue;
-                    const double c = qx->chix[pr];
-                    if (a == axis) lin = fma(c, xo[b], lin);
-                    else if (b == axis) lin = fma(c, xo[a], lin);
-                    else th0 = fma(c, xo[a] * xo[b], th0);
-                }
-            }
-            const double chia = q.chi[axis], loa = I.lo[axis], dxa = I.dx[axis];
-            const double *va = vtab + ((size_t)inst * 3 + axis) * vtab_stride;
-            const double wv0 = q.w * v0;
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                const int i = tl + c * T;
-                const double x = loa + (double)i * dxa;
-                double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
-                // eps V_I: the caller's value at the point, or the factor form
-                const double rest = fma(q.s, a2, th0);
-                const double bv = vi ? fma(q.w, vi[I.offset + base + i * estr], rest) : fma(wv0, va[i], rest);
-                double th = fma(x, fma(chia, 0.5 * x, lin), bv);
-                u[c] = cmul(u[c], cis_neg_tab(th, ctab));
-                // keep the scheduler from interleaving all P phase evaluations
-                // (register pressure); pairs still overlap
-                if (c & 1) __builtin_amdgcn_sched_barrier(0);
-            }
-        };
-
-        if constexpr (MODE == 2) xphase(rec_open[inst], recx_open ? recx_open + inst : nullptr);
-        if constexpr (KIND != kPassInv) fft.template run<-1>(u);
-        if constexpr (KIND == kPassSep) {
-#pragma unroll
-            for (int c = 0; c < P; ++c) u[c] = cmul(u[c], kfl[tl + c * T]);
-        }
-        if constexpr (KIND == kPassMid) {
-            // whole drift k^T G k / 2 with the other wavenumbers of the pencil
-            // fixed: c0 + k_a (c1 + G_aa k_a / 2); scaled by 1 / N_total
-            const RecX &qx = recx[((size_t)inst * rec_steps + step) * m + stage];
-            double ko[3] = {0.0, 0.0, 0.0};
-            double scale = invN;
-            int shift = 0;
-            for (int j = 0; j < sh.ndim; ++j) {
-                if (j != axis) {
-                    const int i = (base >> shift) & (sh.n[j] - 1);
-                    const int sq = i - ((i >= (sh.n[j] >> 1)) ? sh.n[j] : 0);
-                    ko[j] = I.kscale[j] * (double)sq;
-                    scale *= 1.0 / (double)sh.n[j];
-                }
-                shift += sh.logn[j];
-            }
-            double c0 = 0.0, c1 = 0.0;
-            for (int j = 0; j < sh.ndim; ++j)
-                if (j != axis) c0 = fma(r.g[j], 0.5 * ko[j] * ko[j], c0);
-#pragma unroll
-            for (int pr = 0; pr < 3; ++pr) {
-                const int a = (pr == 2) ? 1 : 0, b = (pr == 0) ? 1 : 2;
-                if (b >= sh.ndim) continue;
-                const double g = qx.gx[pr];
-                if (a == axis) c1 = fma(g, ko[b], c1);
-                else if (b == axis) c1 = fma(g, ko[a], c1);
-                else c0 = fma(g, ko[a] * ko[b], c0);
-            }
-            const double gaa = r.g[axis], ksa = I.kscale[axis];
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                const int q = tl + c * T;
-                const int sq = q - ((q >= (nj >> 1)) ? nj : 0);
-                const double k = ksa * (double)sq;
-                const double2 f = cis_neg_tab(fma(k, fma(gaa, 0.5 * k, c1), c0), ctab);
-                u[c] = cmul(u[c], make_double2(f.x * scale, f.y * scale));
-            }
-        }
-        if constexpr (KIND != kPassFwd) fft.template run<+1>(u);
-        if constexpr (MODE == 1) xphase(r, recx ? recx + ((size_t)inst * rec_steps + step) * m + stage : nullptr);
-#pragma unroll
-        for (int c = 0; c < P; ++c) u0[(tl + c * T) * estr] = from_d2<Store>(u[c]);
-    }
-}
 
 // Kinetic-energy partial sums along one axis: for every pencil along `axis`,
 // sum_k k_j^2 |FFT_j(u)|^2 / N_j; block b of instance k writes part[k*nblk + b].
@@ -334,18 +74,6 @@ __global__ __launch_bounds__(kThreadsND) void kin_nd_kernel(const InstDev *__res
     }
 }
 
-static NdShape make_shape(const LaunchND &L)
-{
-    NdShape sh;
-    sh.ndim = L.ndim;
-    for (int j = 0; j < 3; ++j) {
-        sh.n[j] = L.n[j];
-        sh.logn[j] = 0;
-        while ((1 << sh.logn[j]) < L.n[j]) ++sh.logn[j];
-    }
-    return sh;
-}
-
 // log2 of the pencils per group of an axis pass: tpb/T pencils, limited by the
 // pencils available (x) or by the contiguous run of x positions (strided axes).
 int nd_group_log(const int *n, int axis, int tpb)
@@ -384,36 +112,23 @@ int nd_threads(const int *n, int axis, int c64)
     return (lg256 < 3 && nd_group_log(n, axis, 512) > lg256) ? 512 : kThreadsND;
 }
 
-template <typename Store, int P, int MAXS, int MODE, int TPB, int KIND>
-static hipError_t launch_pass_tpb(const LaunchND &L)
-{
-    NdShape sh = make_shape(L);
-    int lG = nd_group_log(L.n, L.axis, TPB);
-    int threads = 1 << (lG + sh.logn[L.axis] - Log2<P>::value);
-    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE, TPB, KIND>), dim3(L.grid), dim3(threads), 0, L.stream,
-                       L.insts, L.n_inst, L.rec, L.rec_open, L.recx, L.recx_open, L.vi, L.vtab, L.vtab_stride, L.cistab,
-                       L.twtab, L.twlog, (Store *)L.psi, sh, L.axis, lG, L.stage, L.m, L.rec_steps, L.step,
-                       L.step_base);
-    return hipGetLastError();
-}
-
 template <typename Store, int P, int MAXS, int MODE>
 static hipError_t launch_pass_mode(const LaunchND &L)
 {
     switch (L.kind) {
     case kPassSep:
         if constexpr (P == 8 && sizeof(Store) == 8) {
-            if (nd_threads(L.n, L.axis, 1) == 512) return launch_pass_tpb<Store, P, MAXS, MODE, 512, kPassSep>(L);
+            if (nd_threads(L.n, L.axis, 1) == 512) return launch_pass_tpb<Store, P, MAXS, MODE, 512, kPassSep, 0>(L);
         }
-        return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassSep>(L);
+        return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassSep, 0>(L);
     case kPassFwd:
-        if constexpr (MODE != 1) return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassFwd>(L);
+        if constexpr (MODE != 1) return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassFwd, 0>(L);
         return hipErrorInvalidValue;
     case kPassMid:
-        if constexpr (MODE == 0) return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassMid>(L);
+        if constexpr (MODE == 0) return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassMid, 0>(L);
         return hipErrorInvalidValue;
     case kPassInv:
-        if constexpr (MODE != 2) return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassInv>(L);
+        if constexpr (MODE != 2) return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassInv, 0>(L);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
@@ -447,7 +162,23 @@ static hipError_t launch_pass_store(const LaunchND &L)
 hipError_t launch_nd_pass(const LaunchND &L)
 {
     if (L.n_inst <= 0) return hipSuccess;
+    if (!L.generic && L.kind == kPassSep && !L.apply_open && nd_fixed_shape(L.n, L.axis, L.c64))
+        return launch_nd_pass_fixed(L);
     return L.c64 ? launch_pass_store<float2>(L) : launch_pass_store<double2>(L);
+}
+
+// A separable pass runs a fixed-shape instance when its axis has 128 .. 1024
+// points and a workgroup holds its full complement of pencils (every thread
+// of the TPB-thread group busy).
+bool nd_fixed_shape(const int *n, int axis, int c64)
+{
+    const int na = n[axis];
+    if (na < 128 || na > 1024 || (na & (na - 1)) != 0) return false;
+    const int tpb = nd_threads(n, axis, c64);
+    int logn = 0, ltpb = 0;
+    while ((1 << logn) < na) ++logn;
+    while ((1 << ltpb) < tpb) ++ltpb;
+    return nd_group_log(n, axis, tpb) == ltpb - (logn - 3);
 }
 
 template <typename Store, int P, int MAXS>

@@ -105,10 +105,14 @@ struct LaunchND {
     int axis, stage, m, rec_steps, step;
     const int *step_base;  // device int added to step (graph replay), or null
     int apply_open, apply_close;
-    int grid;  // persistent workgroups
+    int grid;     // persistent workgroups
+    int generic;  // 1: runtime-shaped FFT for every axis length
     hipStream_t stream;
 };
 hipError_t launch_nd_pass(const LaunchND &L);
+// fixed-shape separable passes (kern_nd_fix.hip), for the shapes nd_fixed_shape accepts
+bool nd_fixed_shape(const int *n, int axis, int c64);
+hipError_t launch_nd_pass_fixed(const LaunchND &L);
 // Kinetic energy partials along L.axis: part[inst * nblk + b].
 hipError_t launch_kinetic_nd(const LaunchND &L, int nblk, double *part);
 int points_per_thread_nd(int n);
