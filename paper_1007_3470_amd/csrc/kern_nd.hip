@@ -162,19 +162,27 @@ static hipError_t launch_pass_store(const LaunchND &L)
 hipError_t launch_nd_pass(const LaunchND &L)
 {
     if (L.n_inst <= 0) return hipSuccess;
-    if (!L.generic && L.kind == kPassSep && !L.apply_open && nd_fixed_shape(L.n, L.axis, L.c64))
-        return launch_nd_pass_fixed(L);
+    if (!L.generic && !L.apply_open && nd_fixed_shape(L.n, L.axis, nd_pass_threads(L))) {
+        if (L.kind == kPassSep) return launch_nd_pass_fixed(L);
+        return launch_nd_pass_fixed_coupled(L);
+    }
     return L.c64 ? launch_pass_store<float2>(L) : launch_pass_store<double2>(L);
 }
 
-// A separable pass runs a fixed-shape instance when its axis has 128 .. 1024
-// points and a workgroup holds its full complement of pencils (every thread
-// of the TPB-thread group busy).
-bool nd_fixed_shape(const int *n, int axis, int c64)
+// Threads per workgroup of a pass: 512 only for the separable c64 passes that
+// nd_threads selects, 256 otherwise.
+int nd_pass_threads(const LaunchND &L)
+{
+    return (L.kind == kPassSep && L.c64) ? nd_threads(L.n, L.axis, 1) : kThreadsND;
+}
+
+// A pass runs a fixed-shape instance when its axis has 128 .. 1024 points and
+// a tpb-thread workgroup holds its full complement of pencils (every thread
+// busy).
+bool nd_fixed_shape(const int *n, int axis, int tpb)
 {
     const int na = n[axis];
     if (na < 128 || na > 1024 || (na & (na - 1)) != 0) return false;
-    const int tpb = nd_threads(n, axis, c64);
     int logn = 0, ltpb = 0;
     while ((1 << logn) < na) ++logn;
     while ((1 << ltpb) < tpb) ++ltpb;

@@ -53,7 +53,8 @@ static hipError_t launch_fix_tpb(const LaunchND &L)
 
 hipError_t launch_nd_pass_fixed(const LaunchND &L)
 {
-    if (L.kind != kPassSep || L.apply_open || !nd_fixed_shape(L.n, L.axis, L.c64)) return hipErrorInvalidValue;
+    if (L.kind != kPassSep || L.apply_open || !nd_fixed_shape(L.n, L.axis, nd_pass_threads(L)))
+        return hipErrorInvalidValue;
     if (L.c64) return L.apply_close ? launch_fix_tpb<float2, 1>(L) : launch_fix_tpb<float2, 0>(L);
     return L.apply_close ? launch_fix_tpb<double2, 1>(L) : launch_fix_tpb<double2, 0>(L);
 }

@@ -110,9 +110,12 @@ struct LaunchND {
     hipStream_t stream;
 };
 hipError_t launch_nd_pass(const LaunchND &L);
-// fixed-shape separable passes (kern_nd_fix.hip), for the shapes nd_fixed_shape accepts
-bool nd_fixed_shape(const int *n, int axis, int c64);
+// fixed-shape passes for the shapes nd_fixed_shape accepts: separable
+// (kern_nd_fix.hip) and coupled-trap kinds (kern_nd_fix_coupled.hip)
+int nd_pass_threads(const LaunchND &L);
+bool nd_fixed_shape(const int *n, int axis, int tpb);
 hipError_t launch_nd_pass_fixed(const LaunchND &L);
+hipError_t launch_nd_pass_fixed_coupled(const LaunchND &L);
 // Kinetic energy partials along L.axis: part[inst * nblk + b].
 hipError_t launch_kinetic_nd(const LaunchND &L, int nblk, double *part);
 int points_per_thread_nd(int n);

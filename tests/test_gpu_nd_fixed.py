@@ -1,7 +1,9 @@
-"""Fixed-shape separable axis passes (axes of 128 .. 1024 points): the same
-bits as the runtime-shaped passes (nd_generic), and oracle parity, on shapes
-that reach every fixed-shape instance (padded-row and interleaved layouts,
-256- and 512-thread groups, drift-only and closing x-phase passes)."""
+"""Fixed-shape axis passes (axes of 128 .. 1024 points): the same bits as the
+runtime-shaped passes (nd_generic), and oracle parity, on shapes that reach
+every fixed-shape instance: separable passes (padded-row and interleaved
+layouts, 256- and 512-thread groups, drift-only and closing x-phase) and the
+coupled-trap kinds (forward, forward + whole drift + inverse, inverse with and
+without the closing x-phase)."""
 from dataclasses import replace
 
 import numpy as np
@@ -42,6 +44,13 @@ def reshaped(shape, n_inst, nsteps, seed=0):
         out.append(i2)
         psis.append(W._normalise(i2, (np.exp(-r2 / 2) * (1 + 0.1j * m[0])).astype(complex)))
     return replace(base, instances=out, psi0=psis)
+
+
+def coupled(shape, n_inst, nsteps, rule="cf4"):
+    """The coupled-trap recipes (off-diagonal W) on another grid shape."""
+    w = reshaped(shape, n_inst, nsteps)
+    wc = (0.3, 0.2, -0.25) if shape[2] > 1 else (0.4, 0.0, 0.0)
+    return replace(w, instances=[replace(i, wcross=wc) for i in w.instances], ho_rule=rule)
 
 
 def run(pkg, w, dtype, **kw):
@@ -92,4 +101,35 @@ def test_fixed_oracle_parity(pkg, shape, n_inst, dtype):
         ref = oracle.evolve(inst, w.psi0[k], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
         err = W.rel_l2(got[k], ref)
         say("fixed-shape %s k=%d %s rel_l2 %.3e" % (shape, k, dtype, err))
+        assert err < (1e-11 if dtype == "c128" else 5e-5)
+
+
+COUPLED_SHAPES = [
+    ((128, 128, 1), 2),
+    ((1024, 256, 1), 1),
+    ((256, 128, 512), 1),
+    ((128, 512, 128), 1),
+]
+
+
+@pytest.mark.parametrize("shape,n_inst", COUPLED_SHAPES)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_coupled_fixed_equals_generic_bitwise(pkg, shape, n_inst, dtype):
+    w = coupled(shape, n_inst, nsteps=2)
+    say("coupled fixed vs generic %s x%d %s" % (shape, n_inst, dtype))
+    fixed = run(pkg, w, dtype)
+    generic = run(pkg, w, dtype, nd_generic=True)
+    for a, b in zip(fixed, generic):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("shape,rule", [((128, 128, 1), "cf4"), ((128, 256, 1), "fsplit"),
+                                        ((128, 128, 16), "cf4")])
+def test_coupled_fixed_oracle_parity(pkg, shape, rule):
+    w = coupled(shape, 1, nsteps=3, rule=rule)
+    for dtype in ("c128", "c64"):
+        got = run(pkg, w, dtype)
+        ref = oracle.evolve(w.instances[0], w.psi0[0], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
+        err = W.rel_l2(got[0], ref)
+        say("coupled fixed-shape %s %s %s rel_l2 %.3e" % (shape, rule, dtype, err))
         assert err < (1e-11 if dtype == "c128" else 5e-5)
