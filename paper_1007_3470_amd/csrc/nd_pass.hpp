@@ -88,7 +88,10 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     constexpr int LDS_ELEMS = (FIX != 0 && FSTRIDED) ? TPB * P : TPB * P + ((TPB * P) >> kPadShift);
     __shared__ double2 lds[LDS_ELEMS];
     __shared__ CisTable ctab;
-    __shared__ double2 kfl[FIX ? (1 << FLOGN) : kMaxAxisND];  // drift factor of every wavenumber of the axis
+    constexpr int kAxisTab = FIX ? (1 << FLOGN) : kMaxAxisND;
+    __shared__ double2 kfl[kAxisTab];  // drift factor of every wavenumber of the axis
+    // passes with an x-phase: (x_i, V_I factor at x_i) of every point of the axis
+    __shared__ double2 xvt[MODE != 0 ? kAxisTab : 1];
     load_cis_table(&ctab, cistab);
     __syncthreads();
 
@@ -183,15 +186,23 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
         }
         const InstDev &I = insts[inst];
         const Rec &r = rec[((size_t)inst * rec_steps + step) * m + stage];
-        if constexpr (KIND == kPassSep) {
+        if constexpr (KIND == kPassSep || MODE != 0) {
             if (inst != kf_inst) {  // uniform across the workgroup
-                const double gk = r.g[axis], ks = I.kscale[axis];
                 __syncthreads();
-                for (int q = threadIdx.x; q < nj; q += blockDim.x) {
-                    int sq = q - ((q >= (nj >> 1)) ? nj : 0);
-                    double k = ks * (double)sq;
-                    double2 f = cis_neg_tab(gk * (0.5 * k * k), ctab);
-                    kfl[q] = make_double2(f.x * invN, f.y * invN);
+                if constexpr (KIND == kPassSep) {
+                    const double gk = r.g[axis], ks = I.kscale[axis];
+                    for (int q = threadIdx.x; q < nj; q += blockDim.x) {
+                        int sq = q - ((q >= (nj >> 1)) ? nj : 0);
+                        double k = ks * (double)sq;
+                        double2 f = cis_neg_tab(gk * (0.5 * k * k), ctab);
+                        kfl[q] = make_double2(f.x * invN, f.y * invN);
+                    }
+                }
+                if constexpr (MODE != 0) {
+                    const double loa = I.lo[axis], dxa = I.dx[axis];
+                    const double *va = vtab + ((size_t)inst * 3 + axis) * vtab_stride;
+                    for (int q = threadIdx.x; q < nj; q += blockDim.x)
+                        xvt[q] = make_double2(loa + (double)q * dxa, va[q]);
                 }
                 __syncthreads();
                 kf_inst = inst;
@@ -201,7 +212,12 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
 
         // merged x-phase: along a pencil only the pass axis's coordinate varies, so
         // the other axes' chirp and V_I factors are formed once per pencil
-        auto xphase = [&](const Rec &q, const RecX *qx) {
+        // (xpencil, evaluated before the transforms so that its loads overlap
+        // them) and the pass axis's coordinate and V_I factor come from xvt
+        struct XPen {
+            double th0, wv0, lin;
+        };
+        auto xpencil = [&](const Rec &q, const RecX *qx) -> XPen {
             double th0 = 0.0, v0 = I.eps, lin = 0.0;
             double xo[3] = {0.0, 0.0, 0.0};  // coordinates of the pencil off the pass axis
             int shift = 0;
@@ -226,26 +242,39 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
                     else th0 = fma(c, xo[a] * xo[b], th0);
                 }
             }
-            const double chia = q.chi[axis], loa = I.lo[axis], dxa = I.dx[axis];
-            const double *va = vtab + ((size_t)inst * 3 + axis) * vtab_stride;
-            const double wv0 = q.w * v0;
+            return XPen{th0, q.w * v0, lin};
+        };
+        auto xpoints = [&](const Rec &q, const XPen &pen) {
+            const double chia = q.chi[axis];
+            // phase angles of the thread's points, then the factors in batches
+            // of XB (the table reads of a batch in flight together)
+            constexpr int XB = (P >= 4) ? 4 : P;
 #pragma unroll
-            for (int c = 0; c < P; ++c) {
-                const int i = tl + c * T;
-                const double x = loa + (double)i * dxa;
-                double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
-                // eps V_I: the caller's value at the point, or the factor form
-                const double rest = fma(q.s, a2, th0);
-                const double bv = vi ? fma(q.w, vi[I.offset + base + i * estr], rest) : fma(wv0, va[i], rest);
-                double th = fma(x, fma(chia, 0.5 * x, lin), bv);
-                u[c] = cmul(u[c], cis_neg_tab(th, ctab));
-                // keep the scheduler from interleaving all P phase evaluations
-                // (register pressure); pairs still overlap
-                if (c & 1) __builtin_amdgcn_sched_barrier(0);
+            for (int c0 = 0; c0 < P; c0 += XB) {
+                double th[XB];
+#pragma unroll
+                for (int cc = 0; cc < XB; ++cc) {
+                    const int c = c0 + cc;
+                    const int i = tl + c * T;
+                    const double2 xv = xvt[i];
+                    double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
+                    // eps V_I: the caller's value at the point, or the factor form
+                    const double rest = fma(q.s, a2, pen.th0);
+                    const double bv =
+                        vi ? fma(q.w, vi[I.offset + base + i * estr], rest) : fma(pen.wv0, xv.y, rest);
+                    th[cc] = fma(xv.x, fma(chia, 0.5 * xv.x, pen.lin), bv);
+                }
+                cis_apply_batch<XB>(u + c0, th, ctab);
             }
         };
 
-        if constexpr (MODE == 2) xphase(rec_open[inst], recx_open ? recx_open + inst : nullptr);
+        if constexpr (MODE == 2) {
+            const RecX *qx = recx_open ? recx_open + inst : nullptr;
+            xpoints(rec_open[inst], xpencil(rec_open[inst], qx));
+        }
+        XPen pen_close{0.0, 0.0, 0.0};
+        if constexpr (MODE == 1)
+            pen_close = xpencil(r, recx ? recx + ((size_t)inst * rec_steps + step) * m + stage : nullptr);
         if constexpr (KIND != kPassInv) fft.template run<-1>(u);
         if constexpr (KIND == kPassSep) {
 #pragma unroll
@@ -290,7 +319,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
             }
         }
         if constexpr (KIND != kPassFwd) fft.template run<+1>(u);
-        if constexpr (MODE == 1) xphase(r, recx ? recx + ((size_t)inst * rec_steps + step) * m + stage : nullptr);
+        if constexpr (MODE == 1) xpoints(r, pen_close);
 #pragma unroll
         for (int c = 0; c < P; ++c) u0[(tl + c * T) * estr] = from_d2<Store>(u[c]);
     }
