@@ -32,6 +32,21 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(pkg.SYMBOLS)
 
 
+def test_header_is_plain_c99(tmp_path):
+    """The boundary compiles and links from strict C99 (the C driver of the GPU
+    test suite, linked against the library; not run here)."""
+    import subprocess
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    libdir = os.path.join(ROOT, "paper_1007_3470_amd")
+    pkg.load()
+    subprocess.check_call(["gcc", "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror",
+                           "-fsyntax-only", "-x", "c", HEADER])
+    subprocess.check_call(["gcc", "-std=c99", "-O2", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(rocm, "include"), "-D__HIP_PLATFORM_AMD__",
+                           os.path.join(ROOT, "tests", "c_abi_driver.c"), "-o", str(tmp_path / "drv"),
+                           "-L", libdir, "-lhfgpe", "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm"])
+
+
 def test_version_and_status_strings():
     lib = pkg.load()
     ma, mi = ctypes.c_int(), ctypes.c_int()
