@@ -1,0 +1,152 @@
+"""GPU path against exact identities of the nonlinear equation, at the full
+sizes of the d-D workloads (where the oracle cannot follow a whole run):
+
+* Kohn mode: with V_I = 0 the centre of mass of every instance follows the
+  classical oscillator x'' = -W(t) x for any sigma (the mean-field force
+  integrates to zero), so the GPU's <x>, <p> must match a DOP853 solution of
+  that ODE to the commutator-free rule's classical error (~1e-13 at these
+  steps) plus the storage rounding;
+* 2-D breathing mode: <r^2>'' = 4E - 4 w^2 <r^2> in an isotropic 2-D trap.
+
+The observables are computed with NumPy from the GPU's output."""
+import math
+from dataclasses import replace
+
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1007_3470_amd as p
+    p.load()
+    return p
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run(pkg, w, dtype, **kw):
+    import torch
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, use_graph=True, **kw)
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, w.t0, w.nsteps)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    return plan.unpack(buf)
+
+
+def moments(inst, u):
+    rho = np.abs(u) ** 2
+    nrm = rho.sum()
+    xs = np.array([float((x * rho).sum() / nrm) for x in inst.mesh()])
+    uh = np.fft.fftn(u)
+    rh = np.abs(uh) ** 2
+    ps = []
+    for j in range(inst.ndim):
+        L = inst.hi[j] - inst.lo[j]
+        k = 2 * math.pi / L * np.fft.fftfreq(inst.n[j], d=1.0 / inst.n[j])
+        s = [1] * inst.ndim
+        s[inst.ndim - 1 - j] = inst.n[j]
+        ps.append(float((k.reshape(s) * rh).sum() / rh.sum()))
+    return xs, np.array(ps)
+
+
+def omega_t(om, t):
+    v0, a, f, ph = om[:4]
+    return v0 * (1.0 + a * math.sin(f * t + ph))
+
+
+def classical(inst, x0, p0, t0, T):
+    """x' = p/mu, p' = -mu W(t) x with W_jj = omega_j(t)^2, W_ij = wcross."""
+    d, mu = inst.ndim, inst.mu
+    pairs = [(0, 1), (0, 2), (1, 2)]
+
+    def rhs(t, y):
+        x, p = y[:d], y[d:]
+        Wm = np.diag([omega_t(inst.omega[j], t) ** 2 for j in range(d)])
+        for q, (a, b) in enumerate(pairs):
+            if b < d:
+                Wm[a, b] = Wm[b, a] = inst.wcross[q]
+        return np.concatenate([p / mu, -mu * (Wm @ x)])
+
+    sol = solve_ivp(rhs, (t0, t0 + T), np.concatenate([x0, p0]), method="DOP853", rtol=1e-13, atol=1e-14)
+    return sol.y[:d, -1], sol.y[d:, -1]
+
+
+def kohn_check(pkg, w, tol):
+    T = w.dt * w.nsteps
+    for dtype in ("c128", "c64"):
+        got = run(pkg, w, dtype)
+        worst = 0.0
+        for inst, u0, u in zip(w.instances, w.psi0, got):
+            x0, p0 = moments(inst, u0)
+            xc, pc = classical(inst, x0, p0, w.t0, T)
+            x, p = moments(inst, u)
+            worst = max(worst, np.abs(x - xc).max(), np.abs(p - pc).max())
+        say("%s %s: centre of mass vs the classical orbit after %d steps: %.3e" % (w.name, dtype, w.nsteps, worst))
+        assert worst < tol[dtype]
+
+
+def test_kohn_mode_3d_full_size(pkg):
+    """256^3, NI5(8,4) + CF4, omega_j(t) modulated, 500 steps: the 3-D recipe
+    with sigma = 200 on [-10, 10)^3, so that the expanding cloud stays off the
+    periodic boundary (with sigma = 500 on [-8, 8)^3 its edge amplitude reaches
+    1e-3 and the wrap-around moves <x> by 1e-4, in the oracle as on the GPU)."""
+    w = W.gpe_3d(lo=-10.0, hi=10.0, sigma=200.0)
+    w = replace(w, instances=[replace(i, eps=0.0) for i in w.instances])
+    kohn_check(pkg, w, {"c128": 1e-10, "c64": 1e-5})
+
+
+def test_kohn_mode_coupled_2d_full_size(pkg):
+    """16 x 512^2 coupled traps (W_xy = 0.4, omega_y(t) modulated), leapfrog +
+    CF4 applied as two exponentials, sigma ~ 100, 2000 steps, on [-16, 16)^2
+    (on the recipe's [-12, 12)^2 the clouds reach the periodic boundary at 2e-4
+    and the wrap-around moves <x> by 4e-7)."""
+    w = W.coupled_2d(lo=-16.0, hi=16.0)
+    w = replace(w, instances=[replace(i, eps=0.0) for i in w.instances])
+    kohn_check(pkg, w, {"c128": 1e-10, "c64": 1e-5})
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_breathing_mode_2d(pkg, dtype):
+    """Isotropic traps (w = 1.3, 0.9), sigma = 40 and -3, 256^2: <r^2>(T) against
+    E/w^2 + (<r^2>_0 - E/w^2) cos 2wT, E from a NumPy FFT of the initial state."""
+    insts, psis = [], []
+    for w0, sig, c in ((1.3, 40.0, (0.3, -0.2)), (0.9, -3.0, (-0.4, 0.1))):
+        inst = W.Instance(2, (256, 256, 1), (-12.0, -12.0, 0.0), (12.0, 12.0, 1.0),
+                          omega=((w0, 0.0, 0.0, 0.0), (w0, 0.0, 0.0, 0.0), W.CONST_OMEGA),
+                          sigma=(sig, 0.0, 0.0, 0.0))
+        x, y = inst.mesh()
+        u = np.exp(-(1.4 * (x - c[0]) ** 2 + 0.8 * (y - c[1]) ** 2) / 2) * (1.0 + 0j)
+        insts.append(inst)
+        psis.append(W._normalise(inst, u))
+    T, n = 1.5, 300
+    w = W.Workload("breathing_2d", insts, psis, "ni5_84", "exact_const", T / n, n)
+    got = run(pkg, w, dtype)
+    for inst, u0, u in zip(insts, psis, got):
+        h = inst.cell
+        x, y = inst.mesh()
+        r2 = x ** 2 + y ** 2
+        uh = np.fft.fftn(u0)
+        k = 2 * math.pi / 24.0 * np.fft.fftfreq(256, d=1.0 / 256)
+        k2 = k.reshape(1, -1) ** 2 + k.reshape(-1, 1) ** 2
+        rho0 = np.abs(u0) ** 2
+        w0, sig = inst.omega[0][0], inst.sigma[0]
+        E = 0.5 * float((k2 * np.abs(uh) ** 2).sum()) * h / u0.size + 0.5 * w0 ** 2 * float((r2 * rho0).sum()) * h \
+            + 0.5 * sig * float((rho0 ** 2).sum()) * h
+        I0 = float((r2 * rho0).sum()) * h
+        exact = E / w0 ** 2 + (I0 - E / w0 ** 2) * math.cos(2 * w0 * T)
+        got_r2 = float((r2 * np.abs(u) ** 2).sum()) * h
+        err = abs(got_r2 - exact) / exact
+        say("breathing %s sigma=%g: <r^2> %.12f vs %.12f (rel %.2e)" % (dtype, sig, got_r2, exact, err))
+        assert abs(exact - I0) > 0.05
+        assert err < (1e-8 if dtype == "c128" else 1e-5)
