@@ -126,6 +126,19 @@ def _check(rc: int, where: str) -> None:
         raise HfgpeError(rc, where)
 
 
+def _check_device_buffer(buf, dtype, need: int, what: str) -> None:
+    """A tensor handed to the library as a device pointer: on the GPU, of the
+    plan's element type, contiguous and holding at least `need` elements."""
+    if not getattr(buf, "is_cuda", False):
+        raise TypeError("%s must be a CUDA (HIP) tensor" % what)
+    if buf.dtype != dtype:
+        raise TypeError("%s has dtype %s, the plan needs %s" % (what, buf.dtype, dtype))
+    if not buf.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if buf.numel() < need:
+        raise ValueError("%s holds %d elements, the plan needs %d" % (what, buf.numel(), need))
+
+
 def scheme_preset(name: str):
     """(a, b) of a named composition as held by the library."""
     lib = load()
@@ -242,7 +255,8 @@ class Plan:
         import torch
         flat = np.concatenate([np.asarray(p, dtype=np.complex128).ravel() for p in psis]) \
             if self.n_inst else np.zeros(0, np.complex128)
-        assert flat.size == self.offsets[-1]
+        if flat.size != self.offsets[-1]:
+            raise ValueError("pack: %d points given, the plan holds %d" % (flat.size, self.offsets[-1]))
         return torch.from_numpy(flat).to(self.torch_dtype).to("cuda")
 
     def unpack(self, buf) -> List[np.ndarray]:
@@ -251,14 +265,18 @@ class Plan:
                 for k in range(self.n_inst)]
 
     def _ptr(self, buf) -> ctypes.c_void_p:
-        assert buf.is_cuda and buf.dtype == self.torch_dtype and buf.is_contiguous()
-        assert buf.numel() >= self.offsets[-1]
+        """Device address of a state buffer, after checking that the kernels
+        stay inside it (explicit checks: they must hold under python -O)."""
+        _check_device_buffer(buf, self.torch_dtype, int(self.offsets[-1]), "state buffer")
         return ctypes.c_void_p(buf.data_ptr())
 
     # -- the hot path -----------------------------------------------------
     def evolve(self, buf, t0: float, nsteps: int) -> None:
-        _check(self.lib.hfgpe_evolve(self.handle, self._ptr(buf), float(t0), int(nsteps)),
-               "hfgpe_evolve")
+        self._stage_exc = None
+        rc = self.lib.hfgpe_evolve(self.handle, self._ptr(buf), float(t0), int(nsteps))
+        if rc != 0:
+            exc, self._stage_exc = self._stage_exc, None
+            raise HfgpeError(rc, "hfgpe_evolve") from exc
 
     def set_stage_callback(self, fn) -> None:
         """Harmonic-oscillator stages from a Python function
@@ -275,7 +293,8 @@ class Plan:
                 f, g, e = fn(inst, axis, t0, tau, mu)
                 out[0], out[1], out[2] = float(f), float(g), float(e)
                 return 0
-            except Exception:  # noqa: BLE001 - reported to the library as a failed stage
+            except Exception as exc:  # noqa: BLE001 - reported to the library as a failed stage
+                self._stage_exc = exc  # re-raised by evolve() as the cause
                 return 1
 
         self._stage_cb = STAGE_FN(tramp)
@@ -291,8 +310,7 @@ class Plan:
             _check(self.lib.hfgpe_set_potential(self.handle, None), "hfgpe_set_potential")
             return
         import torch
-        assert vi.is_cuda and vi.dtype == torch.float64 and vi.is_contiguous()
-        assert vi.numel() >= self.offsets[-1]
+        _check_device_buffer(vi, torch.float64, int(self.offsets[-1]), "potential")
         self._vi = vi
         _check(self.lib.hfgpe_set_potential(self.handle, ctypes.c_void_p(vi.data_ptr())),
                "hfgpe_set_potential")
@@ -301,7 +319,8 @@ class Plan:
         """Host real arrays (one per instance) -> packed float64 device tensor."""
         import torch
         flat = np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in arrays])
-        assert flat.size == self.offsets[-1]
+        if flat.size != self.offsets[-1]:
+            raise ValueError("pack_real: %d points given, the plan holds %d" % (flat.size, self.offsets[-1]))
         return torch.from_numpy(flat).to("cuda")
 
     def norm(self, buf) -> np.ndarray:
