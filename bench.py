@@ -34,13 +34,20 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hf1d_batch1d.json")
 
 
-def kernel_source_hash() -> str:
+# Sources of a measured kernel's translation unit (the .hip file and every
+# header it includes): a change to any of them makes stored counters stale;
+# host-only changes (the API runtime) do not.
+KERNEL_TU_1D = ("kern_1d.hip", "coeff.hpp", "devmath.hpp", "fft_lds.hpp", "kernels.hpp", "layout.hpp")
+KERNEL_TU_ND = ("nd_pass.hpp", "kern_nd.hip", "kern_nd_fix.hip", "kern_nd_fix_coupled.hip", "coeff.hpp",
+                "devmath.hpp", "fft_lds.hpp", "kernels.hpp", "layout.hpp")
+
+
+def kernel_source_hash(names=KERNEL_TU_1D) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1007_3470_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + f.read())
+    for name in sorted(names):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
 
 

@@ -1119,7 +1119,11 @@ int hfgpe_set_stage_callback(hfgpe_plan *P, hfgpe_stage_fn fn, void *user)
         }
         e = hipEventCreateWithFlags(&P->stage_ev, hipEventDisableTiming);
         if (e != hipSuccess) {
+            // leave the plan as it was: no staging without its event
             g_last_hip_error = (int)e;
+            (void)hipHostFree(P->h_stage);
+            P->h_stage = nullptr;
+            P->stage_ev = nullptr;
             return HFGPE_E_HIP;
         }
     }
@@ -1239,7 +1243,14 @@ int hfgpe_autotune(hfgpe_plan *P, void *d_scratch, int64_t trial_steps, int *cho
     cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    {
+        hipError_t e = hipEventCreate(&e1);
+        if (e != hipSuccess) {
+            g_last_hip_error = (int)e;
+            (void)hipEventDestroy(e0);
+            return HFGPE_E_HIP;
+        }
+    }
     const int saved_profile = P->opts.profile;
     P->opts.profile = 0;
     float best = 0.0f;
