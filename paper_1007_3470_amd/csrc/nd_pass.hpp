@@ -130,10 +130,33 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     int kf_inst = -1;
 
     // each workgroup takes a contiguous range of groups (the drift factors change
-    // only when the instance does; neighbouring pencils share cache lines)
+    // only when the instance does; neighbouring pencils share cache lines).
+    // Strided axes whose group rows are shorter than a 128-byte line: two
+    // workgroups on the same XCD (ids b and b + 8; workgroups are dispatched to
+    // the 8 XCDs round robin) share one range and take its even and odd groups
+    // in step, so both halves of every line are requested together and the
+    // second is served by that XCD's L2 instead of a second HBM read.
     const int64_t total = (int64_t)n_inst * gpi;
-    const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-    const int64_t g_end = (blockIdx.x + 1) * per < total ? (blockIdx.x + 1) * per : total;
+    const bool paired = !xaxis && G * (int)sizeof(Store) < 128 && (gridDim.x & 15) == 0 && total > 1;
+    int64_t j_begin, j_end, gmul, goff;
+    if (paired) {
+        const int b = blockIdx.x, k = b >> 3;
+        const int64_t pair = ((int64_t)(k >> 1) << 3) | (b & 7);
+        const int64_t total2 = (total + 1) >> 1, npairs = gridDim.x >> 1;
+        const int64_t per2 = (total2 + npairs - 1) / npairs;
+        j_begin = pair * per2;
+        j_end = (pair + 1) * per2 < total2 ? (pair + 1) * per2 : total2;
+        gmul = 2;
+        goff = k & 1;
+    } else {
+        const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+        j_begin = blockIdx.x * per;
+        j_end = (blockIdx.x + 1) * per < total ? (blockIdx.x + 1) * per : total;
+        gmul = 1;
+        goff = 0;
+    }
+    // group of range position j (past the last group for the odd half of an odd total)
+    auto group_of = [&](int64_t j) { return j * gmul + goff; };
     const int estr = xaxis ? 1 : (1 << lstride);
     // instance and first element of this thread's pencil in group gq (offsets
     // within an instance fit in 32 bits)
@@ -155,16 +178,17 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     constexpr bool kPrefetch = sizeof(Store) == 8;
     Store nxt[kPrefetch ? P : 1];
     int inst_n = 0, base_n = 0;
-    const int64_t g_begin = blockIdx.x * per;
     if constexpr (kPrefetch) {
-        if (g_begin < g_end) {
-            locate(g_begin, inst_n, base_n);
+        if (j_begin < j_end && group_of(j_begin) < total) {
+            locate(group_of(j_begin), inst_n, base_n);
             const Store *src = psi + insts[inst_n].offset + base_n;
 #pragma unroll
             for (int c = 0; c < P; ++c) nxt[c] = src[(tl + c * T) * estr];
         }
     }
-    for (int64_t gg = g_begin; gg < g_end; ++gg) {
+    for (int64_t j = j_begin; j < j_end; ++j) {
+        const int64_t gg = group_of(j);
+        if (gg >= total) break;  // uniform across the workgroup
         double2 u[P];
         int inst, base;
         if constexpr (kPrefetch) {
@@ -172,8 +196,8 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
             base = base_n;
 #pragma unroll
             for (int c = 0; c < P; ++c) u[c] = to_d2(nxt[c]);
-            if (gg + 1 < g_end) {
-                locate(gg + 1, inst_n, base_n);
+            if (j + 1 < j_end && group_of(j + 1) < total) {
+                locate(group_of(j + 1), inst_n, base_n);
                 const Store *src = psi + insts[inst_n].offset + base_n;
 #pragma unroll
                 for (int c = 0; c < P; ++c) nxt[c] = src[(tl + c * T) * estr];
