@@ -215,6 +215,23 @@ typedef int (*hfgpe_stage_fn)(void *user, int inst, int axis, double t0, double 
                               double *fge);
 int hfgpe_set_stage_callback(hfgpe_plan *plan, hfgpe_stage_fn fn, void *user);
 
+/* Time dependence given by the caller (Sec. 1: omega(t) and sigma(t) are any
+ * functions of time): fn returns, for instance inst, omega_j(t) for which = j
+ * (j < ndim) and sigma(t) for which = 3.  The plan's HO rule samples it where
+ * the rule needs the frequency: omega at the start of each stage for
+ * EXACT_CONST (the caller takes care that it is constant), the Gauss nodes of
+ * CF4 and MAGNUS6, the sub-step nodes of FUNDAMENTAL, and omega^2 at the B
+ * times for FSPLIT; sigma is sampled at the B times.  The parameters' omega
+ * and sigma forms are then ignored.  Like hfgpe_set_stage_callback, fn runs
+ * on the host for each chunk of steps, and the two are exclusive: setting
+ * one clears the other.  An omega that is not finite and positive makes
+ * hfgpe_evolve fail with NONPOSITIVE_FREQ, a stage beyond the rule's
+ * singular bound with SINGULAR, a non-finite sigma or coefficient with
+ * NONFINITE.  fn = NULL restores the parameters' forms.  Diagonal traps only
+ * (INVALID_ARG for coupled plans). */
+typedef double (*hfgpe_coef_fn)(void *user, int inst, int which, double t);
+int hfgpe_set_coef_callback(hfgpe_plan *plan, hfgpe_coef_fn fn, void *user);
+
 /* Perturbation as a device array (Sec. 1: V_I is any potential; the B flow of
  * Lemma 1 is pointwise): d_vi holds eps V_I(x) in FP64 at every grid point of
  * every instance, in the packed layout of the state (hfgpe_instance_offsets),

@@ -29,6 +29,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "si
 SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", "hfgpe_evolve",
            "hfgpe_norm", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
            "hfgpe_stage_coeffs_coupled", "hfgpe_set_potential", "hfgpe_set_stage_callback",
+           "hfgpe_set_coef_callback",
            "hfgpe_scheme_preset",
            "hfgpe_device_status", "hfgpe_profile", "hfgpe_autotune", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
 
@@ -80,6 +81,8 @@ class Options(ctypes.Structure):
 # int fn(void *user, int inst, int axis, double t0, double tau, double mu, double *fge)
 STAGE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                             ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double))
+# double fn(void *user, int inst, int which, double t)
+COEF_FN = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double)
 
 _lib = None
 
@@ -102,6 +105,7 @@ def load() -> ctypes.CDLL:
     lib.hfgpe_norm.argtypes = [vp, vp, dp]
     lib.hfgpe_set_potential.argtypes = [vp, vp]
     lib.hfgpe_set_stage_callback.argtypes = [vp, STAGE_FN, vp]
+    lib.hfgpe_set_coef_callback.argtypes = [vp, COEF_FN, vp]
     lib.hfgpe_energy.argtypes = [vp, vp, ctypes.c_double, dp]
     lib.hfgpe_stage_coeffs.argtypes = [vp, ctypes.c_int, ctypes.c_double, dp]
     lib.hfgpe_stage_coeffs_params.argtypes = [ctypes.POINTER(Params), ctypes.c_int,
@@ -298,8 +302,30 @@ class Plan:
                 return 1
 
         self._stage_cb = STAGE_FN(tramp)
+        self._coef_cb = None
         _check(self.lib.hfgpe_set_stage_callback(self.handle, self._stage_cb, None),
                "hfgpe_set_stage_callback")
+
+    def set_coef_callback(self, fn) -> None:
+        """Time dependence from a Python function fn(inst, which, t): omega_j(t)
+        for which = j < ndim, sigma(t) for which = 3, sampled by the plan's HO
+        rule on the host; None restores the parameters' forms.  Setting it
+        clears a stage callback (and the other way round)."""
+        if fn is None:
+            self._coef_cb = None
+            _check(self.lib.hfgpe_set_coef_callback(self.handle, COEF_FN(), None), "hfgpe_set_coef_callback")
+            return
+
+        def tramp(user, inst, which, t):
+            try:
+                return float(fn(inst, which, t))
+            except Exception as exc:  # noqa: BLE001 - a NaN makes the library fail the chunk
+                self._stage_exc = exc  # re-raised by evolve() as the cause
+                return float("nan")
+
+        self._coef_cb = COEF_FN(tramp)
+        self._stage_cb = None
+        _check(self.lib.hfgpe_set_coef_callback(self.handle, self._coef_cb, None), "hfgpe_set_coef_callback")
 
     def set_potential(self, vi) -> None:
         """Use a device tensor of eps V_I per point (float64, the state's packed

@@ -67,9 +67,14 @@ __host__ __device__ inline Fge fge_exact(double mu, double w, double tau)
     return r;
 }
 
+// The rules below take omega(t) as any type with tf_square(om, t) and
+// tf_value(om, t) found by argument-dependent lookup: the instance's TFunc
+// forms on the device, or a caller's host function of t.
+
 // Eq. CommutatorFree (fourth order) with Gauss-Legendre nodes on the stage
 // interval, decomposed by Theorem 2.  The factor with omega_R acts first.
-__host__ __device__ inline Fge fge_cf4(double mu, const TFunc &om, double t0, double tau)
+template <class Om>
+__host__ __device__ inline Fge fge_cf4(double mu, const Om &om, double t0, double tau)
 {
     Fge r{0.0, 0.0, 0.0, 0};
     const double r3 = 1.7320508075688772;  // sqrt(3)
@@ -100,7 +105,8 @@ struct Magnus6 {
     double alpha, beta, gamma;
 };
 
-__host__ __device__ inline Magnus6 magnus6_generator(const TFunc &om, double t0, double tau)
+template <class Om>
+__host__ __device__ inline Magnus6 magnus6_generator(const Om &om, double t0, double tau)
 {
     const double r15 = 3.872983346207417;  // sqrt(15)
     double w1 = tf_square(om, t0 + (0.5 - r15 / 10.0) * tau);
@@ -117,7 +123,8 @@ __host__ __device__ inline Magnus6 magnus6_generator(const TFunc &om, double t0,
 }
 
 // Sixth-order Magnus rule decomposed by Theorem 1.
-__host__ __device__ inline Fge fge_magnus6(double mu, const TFunc &om, double t0, double tau)
+template <class Om>
+__host__ __device__ inline Fge fge_magnus6(double mu, const Om &om, double t0, double tau)
 {
     Fge r{0.0, 0.0, 0.0, 0};
     const Magnus6 M = magnus6_generator(om, t0, tau);
@@ -143,7 +150,8 @@ __host__ __device__ inline Fge fge_magnus6(double mu, const TFunc &om, double t0
 // deviation from I so 1 - S11 and 1 - S22 keep full relative accuracy; the factorisation
 // S = K(f) D(g) K(e) gives g = S12, e = (1 - S11)/S12, f = (1 - S22)/S12, then the
 // canonical scaling to mu.
-__host__ __device__ inline Fge fge_fundamental(double mu, const TFunc &om, double t0, double tau, int q)
+template <class Om>
+__host__ __device__ inline Fge fge_fundamental(double mu, const Om &om, double t0, double tau, int q)
 {
     Fge r{0.0, 0.0, 0.0, 0};
     const double s = tau / (double)q;
@@ -182,8 +190,8 @@ __host__ __device__ inline Fge fge_fsplit(double mu, double tau)
     return r;
 }
 
-__host__ __device__ inline Fge fge_stage(int rule, double mu, const TFunc &om, double t0, double tau,
-                                         int substeps)
+template <class Om>
+__host__ __device__ inline Fge fge_stage(int rule, double mu, const Om &om, double t0, double tau, int substeps)
 {
     switch (rule) {
     case 0: return fge_exact(mu, tf_value(om, t0), tau);

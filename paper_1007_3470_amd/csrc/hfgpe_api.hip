@@ -100,6 +100,10 @@ struct hfgpe_plan {
     // host in pinned staging memory, copied per chunk
     hfgpe_stage_fn stage_fn = nullptr;
     void *stage_user = nullptr;
+    // caller's omega_j(t), sigma(t) (hfgpe_set_coef_callback): the plan's rule
+    // evaluated on the host into the same staging records
+    hfgpe_coef_fn coef_fn = nullptr;
+    void *coef_user = nullptr;
     Rec *h_stage = nullptr;
     int cb_steps_cap = 0;
     hipEvent_t stage_ev = nullptr;
@@ -400,24 +404,79 @@ void build_groups_1d(hfgpe_plan &P, bool plain)
 
 }  // namespace
 
-// Records of a chunk from the caller's stage function: the merging of the
-// coefficient kernel (chi = f_i + e_{i+1}; FSAL across steps; B weights and
-// sigma from the plan), evaluated on the host into the staging buffer.
+namespace hfgpe {
+// omega_j(t) of one instance from the caller's host function, as the rules of
+// coeff.hpp consume it (tf_value / tf_square by argument-dependent lookup); a
+// value that is not finite and positive is remembered and reported after the
+// rule has run
+struct HostOmega {
+    hfgpe_coef_fn fn;
+    void *user;
+    int inst, axis;
+    mutable bool bad;
+};
+inline double tf_value(const HostOmega &h, double t)
+{
+    const double w = h.fn(h.user, h.inst, h.axis, t);
+    if (!(w > 0.0) || !std::isfinite(w)) {
+        h.bad = true;
+        return 1.0;
+    }
+    return w;
+}
+inline double tf_square(const HostOmega &h, double t)
+{
+    const double w = tf_value(h, t);
+    return w * w;
+}
+}  // namespace hfgpe
+
+// Records of a chunk built on the host: HO stages from the caller's stage
+// function, or from the plan's rule with the caller's omega(t) and sigma(t);
+// merged as in the coefficient kernel (chi = f_i + e_{i+1}; FSAL across steps;
+// B weights from the scheme; the harmonic potential in B for the Fourier
+// split with a coefficient callback), into the staging buffer.
 static int host_stage_records(hfgpe_plan *P, double t0, int64_t s0, int k, int64_t nsteps)
 {
     const SchemeDev &S = P->scheme;
     const int m = S.m;
     const double dt = P->dt;
+    const bool coef = P->coef_fn != nullptr;
     Rec *rec_open = P->h_stage + (size_t)P->n_inst * k * m;
     for (int inst = 0; inst < P->n_inst; ++inst) {
         const InstDev &I = P->insts[inst];
         const int nd = I.ndim;
         auto stage = [&](double tau0, int i, double *fge) -> int {
             for (int j = 0; j < nd; ++j) {
-                int rc = P->stage_fn(P->stage_user, inst, j, tau0, dt * S.a[i], I.mu, fge + 3 * j);
-                if (rc != 0) return HFGPE_E_INVALID_ARG;
+                if (coef) {
+                    HostOmega h{P->coef_fn, P->coef_user, inst, j, false};
+                    Fge q = fge_stage(S.rule, I.mu, h, tau0, dt * S.a[i], S.substeps);
+                    if (h.bad) return HFGPE_E_NONPOSITIVE_FREQ;
+                    if (q.status) return q.status;
+                    fge[3 * j] = q.f;
+                    fge[3 * j + 1] = q.g;
+                    fge[3 * j + 2] = q.e;
+                } else {
+                    int rc = P->stage_fn(P->stage_user, inst, j, tau0, dt * S.a[i], I.mu, fge + 3 * j);
+                    if (rc != 0) return HFGPE_E_INVALID_ARG;
+                }
                 if (!std::isfinite(fge[3 * j]) || !std::isfinite(fge[3 * j + 1]) || !std::isfinite(fge[3 * j + 2]))
                     return HFGPE_E_NONFINITE;
+            }
+            return HFGPE_OK;
+        };
+        // sigma(t) * w, and the Fourier split's harmonic phase w mu omega_j(t)^2
+        auto b_terms = [&](Rec &r, double t) -> int {
+            const double sg = coef ? P->coef_fn(P->coef_user, inst, 3, t) : tf_value(I.sig, t);
+            if (!std::isfinite(sg)) return HFGPE_E_NONFINITE;
+            r.s = r.w * sg;
+            if (coef && S.rule == HFGPE_FSPLIT) {
+                for (int j = 0; j < nd; ++j) {
+                    HostOmega h{P->coef_fn, P->coef_user, inst, j, false};
+                    const double q = tf_square(h, t);
+                    if (h.bad) return HFGPE_E_NONPOSITIVE_FREQ;
+                    r.chi[j] += r.w * I.mu * q;
+                }
             }
             return HFGPE_OK;
         };
@@ -435,7 +494,8 @@ static int host_stage_records(hfgpe_plan *P, double t0, int64_t s0, int k, int64
                     o.chi[j] = (j < nd) ? cur[3 * j + 2] : 0.0;
                 }
                 o.w = dt * S.b[0];
-                o.s = o.w * tf_value(I.sig, tn);
+                rc = b_terms(o, tn);
+                if (rc) return rc;
                 rec_open[inst] = o;
             }
             Rec *out = P->h_stage + ((size_t)inst * k + s) * m;
@@ -461,7 +521,8 @@ static int host_stage_records(hfgpe_plan *P, double t0, int64_t s0, int k, int64
                     for (int j = 0; j < nd; ++j) r.chi[j] = cur[3 * j];
                     r.w = dt * S.b[m];
                 }
-                r.s = r.w * tf_value(I.sig, tau_next);
+                rc = b_terms(r, tau_next);
+                if (rc) return rc;
                 out[i] = r;
                 if (i < m - 1) std::memcpy(cur, nxt, sizeof(cur));
             }
@@ -891,7 +952,8 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
     if (nsteps == 0 || P->n_inst == 0) return HFGPE_OK;
     if (!d_psi) return HFGPE_E_INVALID_ARG;
     const int m = P->scheme.m;
-    int chunk = (int)std::min<int64_t>(nsteps, P->stage_fn ? P->cb_steps_cap : P->rec_steps_cap);
+    const bool host_records = P->stage_fn || P->coef_fn;
+    int chunk = (int)std::min<int64_t>(nsteps, host_records ? P->cb_steps_cap : P->rec_steps_cap);
     const bool plain = P->opts.plain != 0;
     int per_launch = plain ? 1 : (P->opts.steps_per_launch > 0 ? P->opts.steps_per_launch : chunk);
     for (int64_t s0 = 0; s0 < nsteps; s0 += chunk) {
@@ -911,7 +973,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
         C.nsteps_total = nsteps;
         C.err = P->d_err;
         C.stream = P->stream;
-        if (P->stage_fn) {
+        if (host_records) {
             // the staging buffer is reused: wait for the previous chunk's copy
             if (P->stage_ev_pending) HIP_TRY(hipEventSynchronize(P->stage_ev));
             P->stage_ev_pending = false;
@@ -1102,10 +1164,11 @@ int hfgpe_energy(hfgpe_plan *P, const void *d_psi, double t, double *h_out)
     return HFGPE_OK;
 }
 
-int hfgpe_set_stage_callback(hfgpe_plan *P, hfgpe_stage_fn fn, void *user)
+// Pinned staging for the host-built records of up to 64 MB per chunk, and the
+// event that orders its reuse after the previous chunk's copy.
+static int ensure_staging(hfgpe_plan *P)
 {
-    if (!P || P->coupled) return HFGPE_E_INVALID_ARG;
-    if (fn && P->n_inst > 0 && !P->h_stage) {
+    if (P->n_inst > 0 && !P->h_stage) {
         // pinned staging for up to 64 MB of records per chunk
         const size_t per_step = (size_t)P->n_inst * P->scheme.m * sizeof(Rec);
         P->cb_steps_cap = (int)std::max<size_t>(1, std::min<size_t>(((size_t)64 << 20) / per_step,
@@ -1127,6 +1190,16 @@ int hfgpe_set_stage_callback(hfgpe_plan *P, hfgpe_stage_fn fn, void *user)
             return HFGPE_E_HIP;
         }
     }
+    return HFGPE_OK;
+}
+
+int hfgpe_set_stage_callback(hfgpe_plan *P, hfgpe_stage_fn fn, void *user)
+{
+    if (!P || P->coupled) return HFGPE_E_INVALID_ARG;
+    if (fn) {
+        int rc = ensure_staging(P);
+        if (rc) return rc;
+    }
     if (!fn && P->stage_ev_pending) {
         // the staging buffer may still be read by an earlier copy
         HIP_TRY(hipEventSynchronize(P->stage_ev));
@@ -1134,6 +1207,30 @@ int hfgpe_set_stage_callback(hfgpe_plan *P, hfgpe_stage_fn fn, void *user)
     }
     P->stage_fn = fn;
     P->stage_user = user;
+    if (fn) {
+        P->coef_fn = nullptr;
+        P->coef_user = nullptr;
+    }
+    return HFGPE_OK;
+}
+
+int hfgpe_set_coef_callback(hfgpe_plan *P, hfgpe_coef_fn fn, void *user)
+{
+    if (!P || P->coupled) return HFGPE_E_INVALID_ARG;
+    if (fn) {
+        int rc = ensure_staging(P);
+        if (rc) return rc;
+    }
+    if (!fn && P->stage_ev_pending) {
+        HIP_TRY(hipEventSynchronize(P->stage_ev));
+        P->stage_ev_pending = false;
+    }
+    P->coef_fn = fn;
+    P->coef_user = user;
+    if (fn) {
+        P->stage_fn = nullptr;
+        P->stage_user = nullptr;
+    }
     return HFGPE_OK;
 }
 
