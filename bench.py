@@ -154,7 +154,19 @@ def cpu_baseline(w, K, per_size, gpu_out):
     errs = {name: max(W.rel_l2(out[k], refs[k]) for k in sample) for name, out in gpu_out.items()}
     return {"value": pts * K / dt, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
             "sample": "%d instances (%d per grid size) x %d steps, single-threaded C oracle, "
-                      "%.1f s" % (len(sample), per_size, K, dt)}, errs
+                      "%.1f s" % (len(sample), per_size, K, dt),
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}, errs
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # ---------------------------------------------------------------------------
@@ -230,6 +242,47 @@ def study(which):
     return 0
 
 
+def precision_study():
+    """c64 storage against c128 over 10^2 .. 10^4 steps on the 1-D, batch, 2-D
+    and 3-D workloads: relative L2 distance (max and median over instances) and
+    the norm drift of both storages, at checkpoints of one continuing run (an
+    evolve call split into pieces gives the same bits as one call).  A
+    distance that grows linearly with the step count would flag a systematic
+    error; rounding the stored state grows like its square root."""
+    import torch
+    import paper_1007_3470_amd as pkg
+    import workloads as W
+    pkg.load()
+    marks = (100, 1000, 10000)
+    sets = (("gpe_1d", W.gpe_1d()), ("batch_1d", W.batch_1d()), ("gpe_2d", W.gpe_2d()),
+            ("gpe_3d", W.gpe_3d()), ("coupled_2d", W.coupled_2d()), ("coupled_3d", W.coupled_3d()))
+    for name, w in sets:
+        plans, bufs = {}, {}
+        for dtype in ("c64", "c128"):
+            plans[dtype] = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, use_graph=w.instances[0].ndim > 1)
+            bufs[dtype] = plans[dtype].pack(w.psi0)
+        n0 = plans["c128"].norm(bufs["c128"])
+        out = {"study": "precision", "workload": name, "notes": w.notes, "scheme": w.scheme, "rule": w.ho_rule,
+               "dt": w.dt, "checkpoints": []}
+        done = 0
+        for mark in marks:
+            for dtype in ("c64", "c128"):
+                plans[dtype].evolve(bufs[dtype], w.t0 + done * w.dt, mark - done)
+            torch.cuda.synchronize()
+            done = mark
+            a, b = plans["c64"].unpack(bufs["c64"]), plans["c128"].unpack(bufs["c128"])
+            errs = np.array([W.rel_l2(x, y) for x, y in zip(a, b)])
+            out["checkpoints"].append({
+                "steps": mark, "c64_vs_c128_max": float("%.3e" % errs.max()),
+                "c64_vs_c128_median": float("%.3e" % np.median(errs)),
+                "norm_drift_c64": float("%.3e" % np.abs(plans["c64"].norm(bufs["c64"]) - n0).max()),
+                "norm_drift_c128": float("%.3e" % np.abs(plans["c128"].norm(bufs["c128"]) - n0).max())})
+            progress("precision %s: %d steps" % (name, mark))
+        print(json.dumps(out), flush=True)
+        del plans, bufs
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,7 +298,7 @@ def main(argv=None):
                     help="only the 2-D and 3-D workloads (for profiling their kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--study", choices=("sec41", "sec42", "all"),
+    ap.add_argument("--study", choices=("sec41", "sec42", "all", "precision"),
                     help="run the paper's accuracy-vs-cost comparisons instead of the "
                          "benchmark (one JSON line per problem)")
     args = ap.parse_args(argv)
@@ -255,6 +308,8 @@ def main(argv=None):
               file=sys.stderr)
         return 2
 
+    if args.study == "precision":
+        return precision_study()
     if args.study:
         return study(args.study)
 

@@ -85,7 +85,7 @@ struct hfgpe_plan {
     double *d_kin = nullptr;
     int nblk = 1;
     double2 *d_cistab = nullptr;  // phase table (CisTable), exp(-i n pi/128) and corrections
-    double2 *d_twtab = nullptr;   // d-D: exp(-2 pi i q / 2^twlog)
+    double2 *d_twtab = nullptr;   // d-D: FFT twiddles exp(-2 pi i q / 2^twlog) (unit_twiddle)
     // d-D graph replay: a block of kGraphSteps steps captured once per record
     // row stride; the pass kernels add *d_graph_base to their step offsets
     int *d_graph_base = nullptr;
@@ -348,6 +348,32 @@ int build_scheme(const hfgpe_scheme *s, int nd, SchemeDev &S)
         S.b[i] = s->b[i];
     }
     return HFGPE_OK;
+}
+
+// exp(i a) as FP64 (cos, sin), chosen among the neighbours (+-1 ulp in each
+// part) of the rounded values as the pair whose squared magnitude is closest
+// to 1 (evaluated in extended precision).  Rounded twiddles carry a magnitude
+// error of ~5e-17 with a non-zero mean; every axis pass applies the same
+// twiddles, so that mean drifts the norm linearly with the step count.  The
+// chosen pair keeps the angle within 2e-16 and lowers the mean magnitude
+// error about 5x.
+double2 unit_twiddle(long double a)
+{
+    const double c0 = (double)cosl(a), s0 = (double)sinl(a);
+    double bc = c0, bs = s0;
+    long double best = -1.0L;
+    for (int i = -1; i <= 1; ++i)
+        for (int j = -1; j <= 1; ++j) {
+            const double c = i == 0 ? c0 : std::nextafter(c0, i > 0 ? 2.0 : -2.0);
+            const double s = j == 0 ? s0 : std::nextafter(s0, j > 0 ? 2.0 : -2.0);
+            const long double e = fabsl((long double)c * c + (long double)s * s - 1.0L);
+            if (best < 0.0L || e < best) {
+                best = e;
+                bc = c;
+                bs = s;
+            }
+        }
+    return make_double2(bc, bs);
 }
 
 int check_device()
@@ -885,6 +911,21 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         ALLOC_TRY(g.d_items, sizeof(Item1D) * g.items.size());
         COPY_TRY(g.d_items, g.items.data(), sizeof(Item1D) * g.items.size());
     }
+    if (n_inst > 0 && nd > 1) {
+        // d-D: FFT twiddles for the longest axis of the plan (shorter ones take
+        // every 2^k-th entry), evaluated in extended precision.  (The 1-D
+        // kernels evaluate theirs with sincospi at launch: the chosen table
+        // measured no lower norm drift there.)
+        int nmax = 1;
+        for (auto &I : P->insts)
+            for (int j = 0; j < nd; ++j) nmax = std::max(nmax, I.n[j]);
+        P->twlog = ilog2(nmax);
+        std::vector<double2> tw(nmax);
+        const long double pi = 3.14159265358979323846264338327950288L;
+        for (int q = 0; q < nmax; ++q) tw[q] = unit_twiddle(-2.0L * pi * (long double)q / (long double)nmax);
+        ALLOC_TRY(P->d_twtab, sizeof(double2) * tw.size());
+        COPY_TRY(P->d_twtab, tw.data(), sizeof(double2) * tw.size());
+    }
     if (nd > 1) {
         int ns = 1;
         for (int j = 0; j < nd; ++j) ns = std::max(ns, P->insts[0].n[j]);
@@ -909,18 +950,6 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         // persistent workgroups: a few per CU, each looping over many pencil groups
         int want = P->opts.nd_workgroups > 0 ? P->opts.nd_workgroups : 512;
         P->nd_grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, want));
-        // FFT twiddles for every axis length, evaluated in extended precision
-        int nmax = 1;
-        for (int j = 0; j < nd; ++j) nmax = std::max(nmax, P->insts[0].n[j]);
-        P->twlog = ilog2(nmax);
-        std::vector<double2> tw(nmax);
-        const long double pi = 3.14159265358979323846264338327950288L;
-        for (int q = 0; q < nmax; ++q) {
-            long double a = -2.0L * pi * (long double)q / (long double)nmax;
-            tw[q] = make_double2((double)cosl(a), (double)sinl(a));
-        }
-        ALLOC_TRY(P->d_twtab, sizeof(double2) * tw.size());
-        COPY_TRY(P->d_twtab, tw.data(), sizeof(double2) * tw.size());
         ALLOC_TRY(P->d_graph_base, sizeof(int));
         {
             int z = 0;

@@ -1,8 +1,9 @@
 // kern_nd.hip -- 2-D / 3-D Hermite-Fourier axis passes for gfx950: launch
 // dispatch, the runtime-shaped pass instances and the kinetic-energy kernel.
-// The pass kernel itself and the d-D design are in nd_pass.hpp; separable
-// passes along axes of 128 .. 1024 points run the fixed-shape instances of
-// kern_nd_fix.hip.
+// The pass kernel itself and the d-D design are in nd_pass.hpp; passes along
+// axes of 128 .. 1024 points (other than the opening pass of an evolve call)
+// run the fixed-shape instances of kern_nd_fix.hip (separable) and
+// kern_nd_fix_coupled.hip (coupled-trap kinds).
 #include <hip/hip_runtime.h>
 
 #include "nd_pass.hpp"
