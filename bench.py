@@ -283,6 +283,26 @@ def precision_study():
     return 0
 
 
+def mall_study(steps: int = 1000):
+    """The 1-D batch scaled past the 256 MB MALL (AMD's last-level cache):
+    4096, 16384 and 40960 instances of the batch recipe, c64 and c128, the
+    rate over `steps` steps.  The resident kernel touches HBM once per launch,
+    so the rate should not depend on whether the state fits in the cache."""
+    import torch
+    import paper_1007_3470_amd as pkg
+    import workloads as W
+    pkg.load()
+    for n_inst in (4096, 16384, 40960):
+        w = W.batch_1d(n_inst=n_inst, nsteps=steps)
+        out = {"study": "mall", "instances": n_inst, "grid_points": w.points, "steps": steps}
+        for dtype, sc in (("c64", 8), ("c128", 16)):
+            plan, buf, wall, *_ = timed_evolve(pkg, torch, w, dtype, steps, 20)
+            out[dtype] = {"state_MB": w.points * sc / 1e6, "value": w.points * steps / wall}
+            del plan, buf
+        print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,7 +318,7 @@ def main(argv=None):
                     help="only the 2-D and 3-D workloads (for profiling their kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
-    ap.add_argument("--study", choices=("sec41", "sec42", "all", "precision"),
+    ap.add_argument("--study", choices=("sec41", "sec42", "all", "precision", "mall"),
                     help="run the paper's accuracy-vs-cost comparisons instead of the "
                          "benchmark (one JSON line per problem)")
     args = ap.parse_args(argv)
@@ -310,6 +330,8 @@ def main(argv=None):
 
     if args.study == "precision":
         return precision_study()
+    if args.study == "mall":
+        return mall_study()
     if args.study:
         return study(args.study)
 
