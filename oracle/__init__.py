@@ -26,7 +26,13 @@ Parity status per function (the pins live in ``tests/test_oracle_*.py``):
   evolve          pinned: coherent-state closed form (linear, constant omega),
                   ground-state single step (Fig. 1 experiment), norm
                   conservation, time reversibility, observed order under
-                  step halving, linear time-dependent exact reference
+                  step halving, linear time-dependent exact reference; the
+                  nonlinear evolution against exact identities of the GPE:
+                  the Kohn mode (centre of mass = classical orbit for any
+                  sigma, also coupled and time-dependent) and the 2-D
+                  breathing mode (which fixes the nonlinear coefficient)
+  evolve(vi=...)  pinned: equals the factor form; a linear potential's
+                  shifted ground state (closed form)
   norm, energy    pinned: closed-form Gaussian values
 The absolute trajectory of nonlinear, time-dependent runs has no independent
 exact value; it is trusted through the pins above.
