@@ -323,8 +323,8 @@ def main(argv=None):
                          "benchmark (one JSON line per problem)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(instances would be sharded across GPUs with no exchange); use --gpus 1",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(independent instances would be sharded across GPUs with no exchange); use --gpus 1",
               file=sys.stderr)
         return 2
 
