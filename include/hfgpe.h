@@ -162,7 +162,8 @@ typedef struct {
                               ordered against the default stream) */
     int profile;           /* 1 = bracket every step-kernel launch with HIP
                               events on the plan's stream (hfgpe_profile) */
-    int nd_workgroups;     /* d-D: persistent workgroups per axis pass (0 = auto) */
+    int nd_workgroups;     /* d-D: persistent workgroups per axis pass (0 = per pass, as many
+                              as the device holds at once, at most 2 per CU along x) */
     int nd_generic;        /* d-D: 1 = every axis pass runs the runtime-shaped
                               FFT (by default separable passes along axes of
                               128 .. 1024 points run fixed-shape instances;
@@ -284,7 +285,7 @@ int hfgpe_scheme_preset(const char *name, int *m, double *a, double *b);
 
 /* Pick the plan's schedule by timing candidates with HIP events on its
  * stream: for d-D plans the number of persistent workgroups per axis pass
- * (256 ... 2048), for 1-D plans the steps per resident launch (whole chunk,
+ * (0 = sized per pass as for nd_workgroups = 0, or 256 ... 2048), for 1-D plans the steps per resident launch (whole chunk,
  * 1024 or 256; candidates not shorter than trial_steps are skipped).  d_scratch is a device buffer
  * of the plan's layout holding representative data (its contents are
  * overwritten); trial_steps steps are run per candidate (>= 1).  The winning

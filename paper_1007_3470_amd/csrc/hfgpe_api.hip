@@ -113,7 +113,8 @@ struct hfgpe_plan {
     int vtab_stride = 0;
     double *d_kpart = nullptr;  // d-D kinetic-energy partials
     int kin_nblk = 1;
-    int nd_grid = 1;
+    int nd_grid = 0;  // d-D persistent workgroups per pass; 0: per kernel instance
+    int n_cu = 1;     // compute units of the plan's device
     // profiling: (start, stop) event pairs recorded on the plan's stream
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_coeff, ev_pool;
 
@@ -621,6 +622,7 @@ static int nd_step(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const in
             L.apply_open = (first && i == 0 && pp == 0) ? 1 : 0;
             L.apply_close = (pp == np - 1) ? 1 : 0;
             L.grid = P->nd_grid;
+            L.n_cu = P->n_cu;
             L.generic = P->opts.nd_generic;
             L.stream = P->stream;
             std::pair<hipEvent_t, hipEvent_t> es{};
@@ -947,9 +949,20 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
             int lG = nd_group_log(P->insts[0].n, j, nd_threads(P->insts[0].n, j, dtype == HFGPE_C64));
             groups = std::max<int64_t>(groups, (int64_t)n_inst * ((pts / P->insts[0].n[j]) >> lG));
         }
-        // persistent workgroups: a few per CU, each looping over many pencil groups
-        int want = P->opts.nd_workgroups > 0 ? P->opts.nd_workgroups : 512;
-        P->nd_grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, want));
+        // persistent workgroups, each looping over many pencil groups: by default
+        // (0) every pass launches as many as the device holds at once for its
+        // kernel instance (occupancy x compute units)
+        P->nd_grid = P->opts.nd_workgroups > 0 ? (int)std::max<int64_t>(1, std::min<int64_t>(groups, P->opts.nd_workgroups)) : 0;
+        {
+            int dev = 0;
+            hipError_t e = hipGetDevice(&dev);
+            if (e == hipSuccess) e = hipDeviceGetAttribute(&P->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e != hipSuccess || P->n_cu < 1) {
+                g_last_hip_error = (int)e;
+                delete P;
+                return HFGPE_E_HIP;
+            }
+        }
         ALLOC_TRY(P->d_graph_base, sizeof(int));
         {
             int z = 0;
@@ -1358,8 +1371,10 @@ int hfgpe_autotune(hfgpe_plan *P, void *d_scratch, int64_t trial_steps, int *cho
         for (int j = 0; j < P->ndim; ++j)
             groups = std::max<int64_t>(groups, (int64_t)P->n_inst * ((pts / P->insts[0].n[j]) >>
                                                                     nd_group_log(P->insts[0].n, j, 256)));
+        cand.push_back(0);  // per kernel instance: occupancy x compute units
         for (int g : {256, 512, 768, 1024, 1536, 2048})
-            if (g <= groups || cand.empty()) cand.push_back((int)std::min<int64_t>(g, groups));
+            if (g <= groups) cand.push_back(g);
+        if (cand.size() == 1) cand.push_back((int)groups);
     } else {
         // steps per resident launch: the whole chunk (0) or shorter launches
         for (int64_t k : {(int64_t)0, (int64_t)1024, (int64_t)256})

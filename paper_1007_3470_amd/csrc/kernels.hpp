@@ -105,7 +105,8 @@ struct LaunchND {
     int axis, stage, m, rec_steps, step;
     const int *step_base;  // device int added to step (graph replay), or null
     int apply_open, apply_close;
-    int grid;     // persistent workgroups
+    int grid;     // persistent workgroups; 0: as many as the device holds at once for the pass's kernel
+    int n_cu;     // compute units of the device
     int generic;  // 1: runtime-shaped FFT for every axis length
     hipStream_t stream;
 };

@@ -27,6 +27,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "coeff.hpp"
 #include "devmath.hpp"
 #include "fft_lds.hpp"
@@ -369,7 +371,29 @@ hipError_t launch_pass_tpb(const LaunchND &L)
     int lG = nd_group_log(L.n, L.axis, TPB);
     int threads = 1 << (lG + sh.logn[L.axis] - Log2<P>::value);
     if (FIX != 0 && threads != TPB) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE, TPB, KIND, FIX>), dim3(L.grid), dim3(threads), 0,
+    int grid = L.grid;
+    if (grid <= 0) {
+        // persistent grid sized to what the device holds at once for this
+        // instance (its registers and LDS set the workgroups per CU); a
+        // fixed-shape instance always runs TPB threads, so its figure is kept.
+        // Passes along x (contiguous rows) stay at two per CU: a third made
+        // them 1-4% slower, while strided passes gained 4-13%.
+        static std::atomic<int> fixed_per_cu{0};
+        int per_cu = FIX != 0 ? fixed_per_cu.load(std::memory_order_relaxed) : 0;
+        if (per_cu <= 0) {
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, hfnd_pass_kernel<Store, P, MAXS, MODE, TPB, KIND, FIX>, threads, 0);
+            if (e != hipSuccess) return e;
+            per_cu = per_cu > 0 ? per_cu : 1;
+            if (FIX != 0) fixed_per_cu.store(per_cu, std::memory_order_relaxed);
+        }
+        if (L.axis == 0 && per_cu > 2) per_cu = 2;
+        const int64_t pts = (int64_t)L.n[0] * L.n[1] * L.n[2];
+        const int64_t groups = (int64_t)L.n_inst * ((pts / L.n[L.axis]) >> lG);
+        const int64_t want = (int64_t)per_cu * (L.n_cu > 0 ? L.n_cu : 1);
+        grid = (int)(groups < want ? (groups > 0 ? groups : 1) : want);
+    }
+    hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE, TPB, KIND, FIX>), dim3(grid), dim3(threads), 0,
                        L.stream, L.insts, L.n_inst, L.rec, L.rec_open, L.recx, L.recx_open, L.vi, L.vtab,
                        L.vtab_stride, L.cistab, L.twtab, L.twlog, (Store *)L.psi, sh, L.axis, lG, L.stage, L.m,
                        L.rec_steps, L.step, L.step_base);
