@@ -200,22 +200,29 @@ def test_autotune_keeps_results(pkg):
         assert np.array_equal(got[k], ref[k])
 
 
+@pytest.mark.parametrize("make", [lambda: W.gpe_3d(n=128, nsteps=3),
+                                  lambda: W.gpe_2d(n=512, n_inst=2, nsteps=3),
+                                  lambda: W.coupled_2d(n=256, n_inst=2, nsteps=2)],
+                         ids=["3d_128", "2d_512", "coupled_2d_256"])
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_persistent_grid_does_not_change_results(pkg, dtype):
-    """The default grid (sized per pass from the kernel's occupancy), a
-    multiple of 16 (strided c64 passes pair workgroups on one XCD) and an odd
-    count (no pairing, uneven ranges) give the same bits."""
+def test_persistent_grid_does_not_change_results(pkg, make, dtype):
+    """The default grid (sized per pass from the kernel's occupancy), 512 and
+    15 workgroups give the same bits.  On the 512-point axes (and c64 on
+    256-point ones) the strided rows are shorter than a 128-byte line, so grids
+    that are multiples of 16 pair workgroups on one XCD and 15 does not (each
+    of its workgroups also takes many groups); the 128-point axes never pair."""
     import torch
-    w = W.gpe_3d(n=128, nsteps=3)
+    w = make()
     outs = []
-    for wg in (0, 512, 333):
+    for wg in (0, 512, 15):
         plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, nd_workgroups=wg)
         buf = plan.pack(w.psi0)
         plan.evolve(buf, w.t0, w.nsteps)
         torch.cuda.synchronize()
         assert plan.device_status() == 0
-        outs.append(plan.unpack(buf)[0])
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+        outs.append(plan.unpack(buf))
+    for k in range(len(w.instances)):
+        assert np.array_equal(outs[0][k], outs[1][k]) and np.array_equal(outs[0][k], outs[2][k])
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
