@@ -26,7 +26,7 @@
 namespace hfgpe {
 
 template <typename Store, typename Xch, int P, int MAXS>
-__global__ __launch_bounds__(kThreads1D, 2) void hf1d_kernel(const Item1D *__restrict__ items,
+__global__ __launch_bounds__(kThreads1D, (P <= 8 ? 2 : 1)) void hf1d_kernel(const Item1D *__restrict__ items,
                                                           const int *__restrict__ perm,
                                                           const InstDev *__restrict__ insts,
                                                           const Rec *__restrict__ rec,
