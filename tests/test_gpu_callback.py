@@ -87,6 +87,18 @@ def test_callback_theorem2_matches_cf4_2d(pkg, dtype):
         assert W.rel_l2(got[k], ref) < (1e-11 if dtype == "c128" else 5e-5)
 
 
+def test_callback_with_graph_replay_3d(pkg):
+    """3-D plan with hipGraph replay (16-step blocks and a remainder) fed by the
+    host-staged stage records: the same bits as direct launches, and the
+    oracle's CF4 result."""
+    w = W.gpe_3d(n=32, nsteps=21)
+    _, direct = run(pkg, w, "c128", theorem2(w.instances))
+    _, graphed = run(pkg, w, "c128", theorem2(w.instances), use_graph=True)
+    assert np.array_equal(direct[0], graphed[0])
+    ref = oracle.evolve(w.instances[0], w.psi0[0], w.scheme, "cf4", w.dt, w.t0, w.nsteps)
+    assert W.rel_l2(graphed[0], ref) < 1e-11
+
+
 def test_callback_multi_chunk_batch(pkg):
     """4096 instances: the 64 MB staging holds 256 steps, so 600 steps take three
     chunks; compared with the library's own CF4 rule and the oracle."""
