@@ -78,7 +78,7 @@ def test_coupled_exact_rule_2d(pkg):
     assert W.rel_l2(out[0], np.exp(-0.5j * T * np.sqrt(lam).sum()) * g0) < 1e-11
 
 
-@pytest.mark.parametrize("shape", [(64, 16, 1), (8, 128, 1)])
+@pytest.mark.parametrize("shape", [(64, 16, 1), (8, 128, 1), (32, 1, 1), (1, 32, 1)])
 def test_coupled_anisotropic_shapes(pkg, shape):
     base = W.coupled_2d(n=16, n_inst=2, nsteps=8)
     insts, psis = [], []

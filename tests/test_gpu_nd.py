@@ -58,7 +58,7 @@ def test_2d_small_batch(pkg, dtype):
         assert err < TOL[dtype]
 
 
-@pytest.mark.parametrize("shape", [(128, 32, 1), (8, 256, 1), (2, 8, 1), (64, 2, 1)])
+@pytest.mark.parametrize("shape", [(128, 32, 1), (8, 256, 1), (2, 8, 1), (64, 2, 1), (64, 1, 1), (1, 64, 1)])
 def test_2d_anisotropic_shapes(pkg, shape):
     w = reshape_workload(W.gpe_2d(n=8, n_inst=2, nsteps=12), shape, (-6.0, -5.0, 0.0), (7.0, 5.0, 1.0))
     _, _, got = run_gpu(pkg, w, "c128")
@@ -80,7 +80,7 @@ def test_3d_small(pkg, scheme, rule, dtype):
     assert err < TOL[dtype]
 
 
-@pytest.mark.parametrize("shape", [(16, 64, 8), (4, 2, 32), (64, 16, 128)])
+@pytest.mark.parametrize("shape", [(16, 64, 8), (4, 2, 32), (64, 16, 128), (16, 1, 8), (1, 1, 32)])
 def test_3d_anisotropic_shapes(pkg, shape):
     base = W.gpe_3d(n=8, nsteps=5)
     w = reshape_workload(replace(base, instances=base.instances * 2, psi0=base.psi0 * 2), shape,
