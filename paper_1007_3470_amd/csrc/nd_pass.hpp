@@ -160,18 +160,29 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     // group of range position j (past the last group for the odd half of an odd total)
     auto group_of = [&](int64_t j) { return j * gmul + goff; };
     const int estr = xaxis ? 1 : (1 << lstride);
-    // instance and first element of this thread's pencil in group gq (offsets
-    // within an instance fit in 32 bits)
-    auto locate = [&](int64_t gq, int &inst_q, int &base_q) {
+    // Element (tl + c T) estr of this thread's pencil in group gq sits at
+    // ubase + lane0 + (tl + c T) estr within its instance (offsets within an
+    // instance fit in 32 bits).  ubase (instance, group) and c T estr are the
+    // same for the whole workgroup and stay in scalar registers; the lane part
+    // lane0 + tl estr is the same for every group, so each lane keeps one
+    // 32-bit byte offset instead of one 64-bit address per point (it stays
+    // below 2^31 bytes for every shape the library accepts).
+    const int lane0 = xaxis ? (slot << lnj) : slot;
+    const uint32_t loff = (uint32_t)(lane0 + tl * estr) * (uint32_t)sizeof(Store);
+    auto point = [&](Store *ub, int c) -> Store & {
+        return *reinterpret_cast<Store *>(reinterpret_cast<char *>(ub + (size_t)c * T * estr) + loff);
+    };
+    // instance and workgroup-shared first element of group gq
+    auto locate = [&](int64_t gq, int &inst_q, int &ubase_q) {
         inst_q = (int)(gq / gpi);
         const int64_t g = gq - (int64_t)inst_q * gpi;
         if (xaxis) {
-            base_q = (int)(((g << lg) + slot) << lnj);
+            ubase_q = (int)((g << lg) << lnj);
         } else {
             const int64_t ipo = ((int64_t)1 << lstride) >> lg;  // groups per outer index
-            const int inner = (int)((g % ipo) * G + slot);
+            const int inner = (int)((g % ipo) * G);
             const int outer = (int)(g / ipo);
-            base_q = outer * (nj << lstride) + inner;
+            ubase_q = outer * (nj << lstride) + inner;
         }
     };
     // c64: the next group's points are loaded while the current one is
@@ -179,37 +190,38 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     // cost more in spills than the hidden latency gains)
     constexpr bool kPrefetch = sizeof(Store) == 8;
     Store nxt[kPrefetch ? P : 1];
-    int inst_n = 0, base_n = 0;
+    int inst_n = 0, ubase_n = 0;
     if constexpr (kPrefetch) {
         if (j_begin < j_end && group_of(j_begin) < total) {
-            locate(group_of(j_begin), inst_n, base_n);
-            const Store *src = psi + insts[inst_n].offset + base_n;
+            locate(group_of(j_begin), inst_n, ubase_n);
+            Store *src = psi + insts[inst_n].offset + ubase_n;
 #pragma unroll
-            for (int c = 0; c < P; ++c) nxt[c] = src[(tl + c * T) * estr];
+            for (int c = 0; c < P; ++c) nxt[c] = point(src, c);
         }
     }
     for (int64_t j = j_begin; j < j_end; ++j) {
         const int64_t gg = group_of(j);
         if (gg >= total) break;  // uniform across the workgroup
         double2 u[P];
-        int inst, base;
+        int inst, ubase;
         if constexpr (kPrefetch) {
             inst = inst_n;
-            base = base_n;
+            ubase = ubase_n;
 #pragma unroll
             for (int c = 0; c < P; ++c) u[c] = to_d2(nxt[c]);
             if (j + 1 < j_end && group_of(j + 1) < total) {
-                locate(group_of(j + 1), inst_n, base_n);
-                const Store *src = psi + insts[inst_n].offset + base_n;
+                locate(group_of(j + 1), inst_n, ubase_n);
+                Store *src = psi + insts[inst_n].offset + ubase_n;
 #pragma unroll
-                for (int c = 0; c < P; ++c) nxt[c] = src[(tl + c * T) * estr];
+                for (int c = 0; c < P; ++c) nxt[c] = point(src, c);
             }
         } else {
-            locate(gg, inst, base);
-            const Store *src = psi + insts[inst].offset + base;
+            locate(gg, inst, ubase);
+            Store *src = psi + insts[inst].offset + ubase;
 #pragma unroll
-            for (int c = 0; c < P; ++c) u[c] = to_d2(src[(tl + c * T) * estr]);
+            for (int c = 0; c < P; ++c) u[c] = to_d2(point(src, c));
         }
+        const int base = ubase + lane0;  // this thread's pencil, first element
         const InstDev &I = insts[inst];
         const Rec &r = rec[((size_t)inst * rec_steps + step) * m + stage];
         if constexpr (KIND == kPassSep || MODE != 0) {
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
                 kf_inst = inst;
             }
         }
-        Store *u0 = psi + I.offset + base;
+        Store *u0 = psi + I.offset + ubase;
 
         // merged x-phase: along a pencil only the pass axis's coordinate varies, so
         // the other axes' chirp and V_I factors are formed once per pencil
@@ -347,7 +359,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
         if constexpr (KIND != kPassFwd) fft.template run<+1>(u);
         if constexpr (MODE == 1) xpoints(r, pen_close);
 #pragma unroll
-        for (int c = 0; c < P; ++c) u0[(tl + c * T) * estr] = from_d2<Store>(u[c]);
+        for (int c = 0; c < P; ++c) point(u0, c) = from_d2<Store>(u[c]);
     }
 }
 
@@ -377,7 +389,9 @@ hipError_t launch_pass_tpb(const LaunchND &L)
         // instance (its registers and LDS set the workgroups per CU); a
         // fixed-shape instance always runs TPB threads, so its figure is kept.
         // Passes along x (contiguous rows) stay at two per CU: a third made
-        // them 1-4% slower, while strided passes gained 4-13%.
+        // them 1-4% slower, while strided passes gained 4-13%.  No pass takes
+        // more than three: the forward and inverse kinds that fit four
+        // measured no better with them.
         static std::atomic<int> fixed_per_cu{0};
         int per_cu = FIX != 0 ? fixed_per_cu.load(std::memory_order_relaxed) : 0;
         if (per_cu <= 0) {
@@ -388,6 +402,7 @@ hipError_t launch_pass_tpb(const LaunchND &L)
             if (FIX != 0) fixed_per_cu.store(per_cu, std::memory_order_relaxed);
         }
         if (L.axis == 0 && per_cu > 2) per_cu = 2;
+        if (per_cu > 3) per_cu = 3;
         const int64_t pts = (int64_t)L.n[0] * L.n[1] * L.n[2];
         const int64_t groups = (int64_t)L.n_inst * ((pts / L.n[L.axis]) >> lG);
         const int64_t want = (int64_t)per_cu * (L.n_cu > 0 ? L.n_cu : 1);
