@@ -389,9 +389,11 @@ hipError_t launch_pass_tpb(const LaunchND &L)
         // instance (its registers and LDS set the workgroups per CU); a
         // fixed-shape instance always runs TPB threads, so its figure is kept.
         // Passes along x (contiguous rows) stay at two per CU: a third made
-        // them 1-4% slower, while strided passes gained 4-13%.  No pass takes
-        // more than three: the forward and inverse kinds that fit four
-        // measured no better with them.
+        // them 1-4% slower, while strided passes gained 4-13%.  So do strided
+        // passes whose rows are under 64 bytes (a quarter line or less: with a
+        // third workgroup the c64 fwd+drift+inv pass on 512-point axes read
+        // 1.55x its bytes instead of 1.01x).  No pass takes more than three:
+        // the forward and inverse kinds that fit four measured no better.
         static std::atomic<int> fixed_per_cu{0};
         int per_cu = FIX != 0 ? fixed_per_cu.load(std::memory_order_relaxed) : 0;
         if (per_cu <= 0) {
@@ -401,7 +403,7 @@ hipError_t launch_pass_tpb(const LaunchND &L)
             per_cu = per_cu > 0 ? per_cu : 1;
             if (FIX != 0) fixed_per_cu.store(per_cu, std::memory_order_relaxed);
         }
-        if (L.axis == 0 && per_cu > 2) per_cu = 2;
+        if ((L.axis == 0 || ((1 << lG) * (int)sizeof(Store)) < 64) && per_cu > 2) per_cu = 2;
         if (per_cu > 3) per_cu = 3;
         const int64_t pts = (int64_t)L.n[0] * L.n[1] * L.n[2];
         const int64_t groups = (int64_t)L.n_inst * ((pts / L.n[L.axis]) >> lG);
