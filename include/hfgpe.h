@@ -26,7 +26,9 @@
  *     (float2 for HFGPE_C64, double2 for HFGPE_C128).  Instance k occupies
  *     complex elements [off[k], off[k+1]) (see hfgpe_instance_offsets) in
  *     row-major order with x fastest: element (ix, iy, iz) of instance k is
- *     at off[k] + (iz * n_y + iy) * n_x + ix.
+ *     at off[k] + (iz * n_y + iy) * n_x + ix.  The buffer must be aligned to
+ *     its element size (8 bytes for c64, 16 for c128): hfgpe_evolve,
+ *     hfgpe_norm and hfgpe_energy return INVALID_ARG otherwise.
  *   - Kinetic wavenumbers k_q = 2 pi / L * (q < n/2 ? q : q - n).
  *   - Every function returns an int status: HFGPE_OK (0) or a negative code.
  *     No exception crosses the ABI.  hfgpe_status_string() names a code.
@@ -241,7 +243,8 @@ int hfgpe_set_coef_callback(hfgpe_plan *plan, hfgpe_coef_fn fn, void *user);
  * and keeps it alive and unchanged while work that uses it may run on the
  * plan's stream.  Costs one extra read of 8 bytes per point wherever the
  * x-space phase is applied (every step of the 1-D kernel reads it once per
- * chunk into LDS).  Errors: INVALID_ARG (plan NULL). */
+ * chunk into LDS).  Errors: INVALID_ARG (plan NULL, or d_vi not aligned to 8
+ * bytes). */
 int hfgpe_set_potential(hfgpe_plan *plan, const double *d_vi);
 
 /* Discrete squared norm h^d sum |u|^2 of every instance into the host array

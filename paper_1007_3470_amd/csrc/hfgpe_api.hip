@@ -377,6 +377,14 @@ double2 unit_twiddle(long double a)
     return make_double2(bc, bs);
 }
 
+// a state buffer must hold whole elements at their natural alignment (the
+// kernels move them with 8- and 16-byte vector loads and stores)
+bool state_aligned(const hfgpe_plan *P, const void *p)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    return a % (P->dtype == HFGPE_C64 ? 8u : 16u) == 0;
+}
+
 int check_device()
 {
     int n = 0;
@@ -992,7 +1000,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
 {
     if (!P || nsteps < 0 || !std::isfinite(t0)) return HFGPE_E_INVALID_ARG;
     if (nsteps == 0 || P->n_inst == 0) return HFGPE_OK;
-    if (!d_psi) return HFGPE_E_INVALID_ARG;
+    if (!d_psi || !state_aligned(P, d_psi)) return HFGPE_E_INVALID_ARG;
     const int m = P->scheme.m;
     const bool host_records = P->stage_fn || P->coef_fn;
     int chunk = (int)std::min<int64_t>(nsteps, host_records ? P->cb_steps_cap : P->rec_steps_cap);
@@ -1135,7 +1143,7 @@ int hfgpe_norm(hfgpe_plan *P, const void *d_psi, double *h_out)
 {
     if (!P || (!h_out && P->n_inst > 0)) return HFGPE_E_INVALID_ARG;
     if (P->n_inst == 0) return HFGPE_OK;
-    if (!d_psi) return HFGPE_E_INVALID_ARG;
+    if (!d_psi || !state_aligned(P, d_psi)) return HFGPE_E_INVALID_ARG;
     std::vector<double> part;
     int rc = run_reduce(P, d_psi, 0, 0.0, part);
     if (rc) return rc;
@@ -1151,7 +1159,7 @@ int hfgpe_energy(hfgpe_plan *P, const void *d_psi, double t, double *h_out)
 {
     if (!P || (!h_out && P->n_inst > 0) || !std::isfinite(t)) return HFGPE_E_INVALID_ARG;
     if (P->n_inst == 0) return HFGPE_OK;
-    if (!d_psi) return HFGPE_E_INVALID_ARG;
+    if (!d_psi || !state_aligned(P, d_psi)) return HFGPE_E_INVALID_ARG;
     std::vector<double> kin(P->n_inst, 0.0);
     if (P->ndim > 1) {
         std::vector<double> kp((size_t)P->n_inst * P->kin_nblk);
@@ -1278,7 +1286,7 @@ int hfgpe_set_coef_callback(hfgpe_plan *P, hfgpe_coef_fn fn, void *user)
 
 int hfgpe_set_potential(hfgpe_plan *P, const double *d_vi)
 {
-    if (!P) return HFGPE_E_INVALID_ARG;
+    if (!P || reinterpret_cast<uintptr_t>(d_vi) % alignof(double) != 0) return HFGPE_E_INVALID_ARG;
     P->d_vi = d_vi;
     return HFGPE_OK;
 }

@@ -70,3 +70,26 @@ def test_callback_exception_is_chained(pkg):
     with pytest.raises(pkg.HfgpeError) as e:
         plan.evolve(plan.pack(w.psi0), 0.0, 3)
     assert isinstance(e.value.__cause__, ZeroDivisionError)
+
+
+def test_misaligned_buffers_are_rejected(pkg):
+    """A raw C caller that passes a pointer off its element alignment gets
+    INVALID_ARG before any work is enqueued; the buffer is untouched."""
+    import ctypes
+    import torch
+    w = W.gpe_1d(n=256, nsteps=2)
+    for dtype, size in (("c128", 16), ("c64", 8)):
+        plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt)
+        big = torch.zeros(int(plan.offsets[-1]) + 1, dtype=plan.torch_dtype, device="cuda")
+        big[:int(plan.offsets[-1])] = plan.pack(w.psi0)
+        before = big.clone()
+        off = ctypes.c_void_p(big.data_ptr() + size // 2)
+        assert plan.lib.hfgpe_evolve(plan.handle, off, 0.0, 2) == -1
+        out = (ctypes.c_double * 4)()
+        assert plan.lib.hfgpe_norm(plan.handle, off, out) == -1
+        assert plan.lib.hfgpe_energy(plan.handle, off, 0.0, out) == -1
+        torch.cuda.synchronize()
+        assert torch.equal(big, before)
+        assert plan.device_status() == 0
+    vi = torch.zeros(int(plan.offsets[-1]) + 1, dtype=torch.float64, device="cuda")
+    assert plan.lib.hfgpe_set_potential(plan.handle, ctypes.c_void_p(vi.data_ptr() + 4)) == -1
