@@ -70,6 +70,7 @@ SHAPES = [
     ((128, 1024, 1), 1),    # LOGN 10 interleaved (c64: 512-thread groups)
     ((128, 256, 128), 1),   # 3-D: interleaved drift-only pass (axis 1)
     ((256, 128, 256), 1),
+    ((16, 16, 1024), 1),    # 3-D: longest axis outermost (stride 256 elements)
 ]
 
 
@@ -92,7 +93,8 @@ def test_fixed_graph_replay(pkg):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("shape,n_inst", [((128, 128, 1), 2), ((256, 128, 1), 1), ((128, 256, 16), 1)])
+@pytest.mark.parametrize("shape,n_inst", [((128, 128, 1), 2), ((256, 128, 1), 1), ((128, 256, 16), 1),
+                                           ((16, 16, 1024), 1), ((1024, 8, 16), 1)])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_fixed_oracle_parity(pkg, shape, n_inst, dtype):
     w = reshaped(shape, n_inst, nsteps=4)
@@ -109,6 +111,7 @@ COUPLED_SHAPES = [
     ((1024, 256, 1), 1),
     ((256, 128, 512), 1),
     ((128, 512, 128), 1),
+    ((16, 16, 1024), 1),
 ]
 
 
