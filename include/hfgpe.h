@@ -157,7 +157,8 @@ typedef struct {
     int steps_per_launch;  /* 1-D: time steps per resident launch (0 = all of
                               the evolve call up to an internal cap) */
     int plain;             /* 1 = reference schedule: one launch per step per
-                              grid-size group, no graphs */
+                              grid-size group (1-D), pass launches only (d-D:
+                              use_graph is ignored) */
     int use_graph;         /* 1 = d-D plans replay blocks of 16 steps from a
                               captured hipGraph (a plan on the legacy default
                               stream then runs on a blocking stream of its own,

@@ -1056,7 +1056,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
                 if (rc) return rc;
                 st = 1;
             }
-            if (P->opts.use_graph && k - st >= kGraphSteps) {
+            if (P->opts.use_graph && !plain && k - st >= kGraphSteps) {
                 int rc = nd_graph_ready(P, d_psi, k);
                 if (rc) return rc;
                 HIP_TRY(launch_set_base(P->d_graph_base, st, P->stream));

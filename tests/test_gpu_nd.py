@@ -256,3 +256,25 @@ def test_nd_time_forms(pkg, rule, dtype):
             err = W.rel_l2(got[k], ref)
             say("nd forms %dD %s %s k=%d rel_l2 %.3e" % (inst.ndim, rule, dtype, k, err))
             assert err < TOL[dtype]
+
+
+def test_plain_schedule_launches_every_pass(pkg):
+    """plain = 1 is the reference schedule: with use_graph also set, a d-D plan
+    still launches every pass itself (each one bracketed by profiling events,
+    which captured graphs do not carry) and gives the graph schedule's bits."""
+    import torch
+    w = W.gpe_2d(n=64, n_inst=2, nsteps=40)
+    outs, launches = [], []
+    for plain in (False, True):
+        plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", w.dt, use_graph=True,
+                        plain=plain, profile=True)
+        buf = plan.pack(w.psi0)
+        plan.evolve(buf, w.t0, w.nsteps)
+        torch.cuda.synchronize()
+        launches.append(plan.profile()[2])
+        outs.append(plan.unpack(buf))
+    passes = 2 * w.nsteps  # leapfrog, two axes
+    assert launches[1] == passes
+    assert launches[0] < passes  # the graph blocks are not bracketed
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
