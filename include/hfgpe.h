@@ -165,8 +165,10 @@ typedef struct {
                               ordered against the default stream) */
     int profile;           /* 1 = bracket every step-kernel launch with HIP
                               events on the plan's stream (hfgpe_profile) */
-    int nd_workgroups;     /* d-D: persistent workgroups per axis pass (0 = per pass, as many
-                              as the device holds at once, at most 2 per CU along x) */
+    int nd_workgroups;     /* d-D: persistent workgroups per axis pass (0 =
+                              per pass, as many as the device holds at once:
+                              at most 3 per CU, 2 along x and for strided rows
+                              under 64 bytes) */
     int nd_generic;        /* d-D: 1 = every axis pass runs the runtime-shaped
                               FFT (by default separable passes along axes of
                               128 .. 1024 points run fixed-shape instances;
@@ -255,7 +257,8 @@ int hfgpe_norm(hfgpe_plan *plan, const void *d_psi, double *h_out);
 /* GPE energy of every instance at time t into h_out[4*n_inst]:
  * (total, kinetic, potential, interaction) per instance, with
  *   kinetic     = h^d / N sum_k |k|^2 / (2 mu) |u^_k|^2,
- *   potential   = h^d sum_x (sum_j mu omega_j(t)^2 x_j^2/2 + eps V_I) |u|^2,
+ *   potential   = h^d sum_x ((mu/2) x^T W(t) x + eps V_I) |u|^2, with
+ *                 W_jj = omega_j(t)^2 and the off-diagonal entries wcross,
  *   interaction = h^d sum_x sigma(t)/2 |u|^4.
  * Synchronises the stream. */
 int hfgpe_energy(hfgpe_plan *plan, const void *d_psi, double t, double *h_out);
@@ -289,9 +292,10 @@ int hfgpe_scheme_preset(const char *name, int *m, double *a, double *b);
 
 /* Pick the plan's schedule by timing candidates with HIP events on its
  * stream: for d-D plans the number of persistent workgroups per axis pass
- * (0 = sized per pass as for nd_workgroups = 0, or 256 ... 2048), for 1-D plans the steps per resident launch (whole chunk,
- * 1024 or 256; candidates not shorter than trial_steps are skipped).  d_scratch is a device buffer
- * of the plan's layout holding representative data (its contents are
+ * (0 = sized per pass as for nd_workgroups = 0, or 256 ... 2048), for 1-D
+ * plans the steps per resident launch (whole chunk, 1024 or 256; candidates
+ * not shorter than trial_steps are skipped).  d_scratch is a device buffer of
+ * the plan's layout holding representative data (its contents are
  * overwritten); trial_steps steps are run per candidate (>= 1).  The winning
  * setting is kept in the plan and written to *choice (may be NULL).
  * Synchronises the stream. */
