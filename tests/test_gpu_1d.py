@@ -141,6 +141,27 @@ def test_schedules_agree_bitwise_fp64(pkg):
         assert np.array_equal(alone[0], a[k]), k
 
 
+def test_autotune_1d_keeps_results(pkg):
+    """hfgpe_autotune on a 1-D plan times the resident-launch lengths (whole
+    chunk, 1024, 256 steps; those not shorter than the trial are skipped) and
+    keeps the fastest; in FP64 storage every split gives the same bits."""
+    import torch
+    w = W.batch_1d(n_inst=48, sizes=(256, 512, 1024, 2048), nsteps=300, seed=23)
+    _, _, ref = run_gpu(pkg, w, "c128")
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", w.dt)
+    choice = plan.autotune(w.psi0, trial_steps=1500)
+    say("1-D autotune chose %d steps per launch (0: the whole chunk)" % choice)
+    assert choice in (0, 1024, 256)
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, w.t0, w.nsteps)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    for a, b in zip(plan.unpack(buf), ref):
+        assert np.array_equal(a, b)
+    # a trial shorter than every fixed length leaves only the whole chunk
+    assert plan.autotune(w.psi0, trial_steps=100) == 0
+
+
 def test_evolve_split_equals_single_call(pkg):
     import torch
     w = W.batch_1d(n_inst=5, sizes=(256, 1024), nsteps=40, seed=8)
