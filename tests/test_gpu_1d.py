@@ -61,6 +61,29 @@ def test_coherent_state_full_run(pkg):
     assert e_orc < 1e-11 and e_ex < 1e-12
 
 
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-13), ("c64", 1e-7)])
+def test_fig1_single_step_ground_state(pkg, dtype, tol):
+    """The Fig. 1 experiment on the GPU: the ground state on [-10, 10) with
+    N = 1024, mu = omega = 1, advanced by one step of size T with the Lemma 2
+    split is exp(-iT/2) times itself to round-off for |T| < pi, forward and
+    backward (the chirp tan(T/2) reaches 14 at T = 3)."""
+    import torch
+    inst = W.Instance(1, (1024, 1, 1), (-10.0, 0.0, 0.0), (10.0, 1.0, 1.0))
+    x = inst.axis(0)
+    g0 = math.pi ** -0.25 * np.exp(-x * x / 2) * (1.0 + 0j)
+    for T in (-3.0, -2.0, -0.25, 0.25, 1.0, 2.5, 3.0):
+        plan = pkg.Plan([inst], "leapfrog", "exact_const", dtype, T)
+        buf = plan.pack([g0])
+        plan.evolve(buf, 0.0, 1)
+        torch.cuda.synchronize()
+        assert plan.device_status() == 0
+        got = plan.unpack(buf)[0]
+        err = W.rel_l2(got, np.exp(-0.5j * T) * g0)
+        ref = oracle.evolve(inst, g0, "leapfrog", "exact_const", T, 0.0, 1)
+        say("Fig. 1 %s T=%g: vs exact %.2e, vs oracle %.2e" % (dtype, T, err, W.rel_l2(got, ref)))
+        assert err < tol and W.rel_l2(got, ref) < tol
+
+
 # ---------------------------------------------------------------------------
 # the 1-D GPE with time-dependent trap: full 10^4 steps, both precisions
 # ---------------------------------------------------------------------------
