@@ -49,3 +49,20 @@ def test_hermite_vs_fourier_split(pkg, sigma, scheme, nsteps, lo, hi):
           % (sigma, scheme, nsteps, err_h, err_f, ratio), flush=True)
     assert err_h < 1e-2 and err_f < 1e-1  # both resolve the solution at this cost
     assert ratio > lo and (hi is None or ratio < hi)
+
+
+@pytest.mark.parametrize("form", ["cos", "pulse"])
+def test_time_dependent_traps(pkg, form):
+    """Sec. 4.2 (Figs. 7-8), NI5(8,4) with 50 steps over T = 5 (250 FFT
+    pairs): the HO split with any HO rule beats the Fourier split by orders of
+    magnitude on both traps.  On the faster pulse the HO rule's own error
+    shows: the sixth-order Magnus rule beats CF4, and the exact
+    fundamental-matrix rule beats both.  Reference: RKN6_4 with the
+    fundamental rule at 2^14 steps."""
+    ref = final_state(pkg, W.timedep_1d(form=form, nsteps=1 << 14, scheme="srkn6_4", rule="fundamental"))
+    err = {rule: W.rel_l2(final_state(pkg, W.timedep_1d(form=form, nsteps=50, scheme="ni5_84", rule=rule)), ref)
+           for rule in ("fsplit", "cf4", "magnus6", "fundamental")}
+    print("%s trap: %s" % (form, ", ".join("%s %.2e" % kv for kv in err.items())), flush=True)
+    assert err["fsplit"] > 100 * max(err["cf4"], err["magnus6"], err["fundamental"])
+    if form == "pulse":
+        assert err["cf4"] > 1.5 * err["magnus6"] and err["magnus6"] > err["fundamental"]
