@@ -66,3 +66,20 @@ def test_time_dependent_traps(pkg, form):
     assert err["fsplit"] > 100 * max(err["cf4"], err["magnus6"], err["fundamental"])
     if form == "pulse":
         assert err["cf4"] > 1.5 * err["magnus6"] and err["magnus6"] > err["fundamental"]
+
+
+def test_second_vs_fourth_order_crossover(pkg):
+    """Sec. 4.1 at sigma = 0.01 (Fig. 4-5): with the HO split the (8,2) method
+    NI4 is the cheaper one at low accuracy and the (8,4) method NI5 at high
+    accuracy: at 40 FFT pairs NI4 (10 steps) has the smaller error than NI5
+    (8 steps), at 400 pairs (100 and 80 steps) the larger."""
+    ref = final_state(pkg, W.perturbed_1d(sigma=0.01, nsteps=8192, scheme="ni5_84", rule="exact_const"))
+
+    def err(scheme, nsteps):
+        return W.rel_l2(final_state(pkg, W.perturbed_1d(sigma=0.01, nsteps=nsteps, scheme=scheme,
+                                                      rule="exact_const")), ref)
+    low = (err("ni4_82", 10), err("ni5_84", 8))
+    high = (err("ni4_82", 100), err("ni5_84", 80))
+    print("40 pairs: NI4 %.2e, NI5 %.2e; 400 pairs: NI4 %.2e, NI5 %.2e" % (low + high), flush=True)
+    assert 3 * low[0] < low[1]     # measured 8.8e-6 vs 1.6e-4
+    assert 10 * high[1] < high[0]  # measured 6.6e-11 vs 1.3e-8
