@@ -272,3 +272,17 @@ def test_coupled_validation():
     # a 1-D instance ignores wcross
     c1 = replace(W.gpe_1d(n=64, nsteps=0).instances[0], wcross=(0.5, 0.0, 0.0))
     assert _gpu_or_nodevice(_create([c1]))
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises; there is no CPU
+    fallback anywhere on the product path."""
+    monkeypatch.setattr(pkg, "_lib", None)
+    monkeypatch.setattr(pkg, "LIB_PATH", str(tmp_path / "libhfgpe.so"))
+    with pytest.raises(ImportError):
+        pkg.load()
+    w = W.gpe_1d(n=64, nsteps=1)
+    with pytest.raises(ImportError):
+        pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", w.dt)
+    with pytest.raises(ImportError):
+        pkg.scheme_preset("leapfrog")
