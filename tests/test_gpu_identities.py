@@ -183,3 +183,14 @@ def test_energy_bounded_autonomous_2d_full_size(pkg, dtype, tol):
     assert worst < tol
     # the run did move: the state is far from its initial value
     assert W.rel_l2(plan.unpack(buf)[0], w.psi0[0]) > 1e-2
+
+
+def test_kohn_mode_coupled_general_mass(pkg):
+    """mu = 1.4 in a coupled trap: the centre of mass follows x' = p/mu,
+    p' = -mu W(t) x (DOP853), so a wrong power of mu in the chirps, the drift
+    or the cross terms shows up.  The grid must resolve the sigma ~ 100 cloud:
+    in the oracle the deviation is 8e-4 at 128^2, 7e-9 at 256^2 and 3e-15 at
+    512^2 (aliasing breaks the discrete identity)."""
+    w = W.coupled_2d(n=512, n_inst=2, lo=-16.0, hi=16.0, nsteps=400)
+    w = replace(w, instances=[replace(i, eps=0.0, mu=1.4) for i in w.instances])
+    kohn_check(pkg, w, {"c128": 1e-10, "c64": 1e-5})

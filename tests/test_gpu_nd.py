@@ -278,3 +278,31 @@ def test_plain_schedule_launches_every_pass(pkg):
     assert launches[0] < passes  # the graph blocks are not bracketed
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("make,mu,rules", [
+    (lambda: W.gpe_2d(n=64, n_inst=2, nsteps=10), 1.7, ("cf4", "magnus6", "fsplit")),
+    (lambda: W.gpe_3d(n=32, nsteps=4), 0.6, ("cf4", "magnus6", "fsplit")),
+    (lambda: W.coupled_2d(n=64, n_inst=2, nsteps=10), 1.4, ("cf4", "fsplit")),
+], ids=["2d", "3d", "coupled_2d"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_general_mass_nd(pkg, make, mu, rules, dtype):
+    """mu != 1 in 2-D, 3-D and coupled grids (the canonical scaling of the HO
+    factors and the drift 1/mu), every rule against the oracle, and the energy."""
+    import torch
+    base = make()
+    insts = [replace(i, mu=mu) for i in base.instances]
+    for rule in rules:
+        w = replace(base, instances=insts, ho_rule=rule)
+        plan, buf, got = run_gpu(pkg, w, dtype)
+        for k, inst in enumerate(insts):
+            ref = oracle.evolve(inst, w.psi0[k], w.scheme, rule, w.dt, w.t0, w.nsteps)
+            err = W.rel_l2(got[k], ref)
+            say("mu=%g %s %s k=%d rel_l2 %.2e" % (mu, rule, dtype, k, err))
+            assert err < TOL[dtype]
+    if dtype == "c128":
+        T = w.t0 + w.dt * w.nsteps
+        e = plan.energy(buf, T)
+        for k, inst in enumerate(insts):
+            eo = oracle.energy(inst, got[k], T)
+            assert np.allclose(e[k], eo, rtol=1e-12, atol=1e-12)
