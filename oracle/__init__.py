@@ -34,6 +34,10 @@ Parity status per function (the pins live in ``tests/test_oracle_*.py``):
   evolve(vi=...)  pinned: equals the factor form; a linear potential's
                   shifted ground state (closed form)
   norm, energy    pinned: closed-form Gaussian values
+  scheme_coefficients
+                  pinned: sums, palindromes and quadrature moments of the
+                  B weights; the values printed in Table tab.1 (stored with
+                  their citation under tests/golden/)
 The absolute trajectory of nonlinear, time-dependent runs has no independent
 exact value; it is trusted through the pins above.
 """
