@@ -306,3 +306,26 @@ def test_general_mass_nd(pkg, make, mu, rules, dtype):
         for k, inst in enumerate(insts):
             eo = oracle.energy(inst, got[k], T)
             assert np.allclose(e[k], eo, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_instances_with_different_boxes(pkg, dtype):
+    """Instances of one d-D plan share the grid shape, not the box: per
+    instance coordinates, wavenumber scales and drift factors (recomputed
+    whenever a workgroup's range crosses into another instance)."""
+    base = W.gpe_2d(n=128, n_inst=3, nsteps=12)
+    boxes = (((-12.0, -12.0), (12.0, 12.0)), ((-8.0, -6.0), (10.0, 9.0)), ((-15.0, -3.0), (5.0, 13.0)))
+    insts, psis = [], []
+    for k, (inst, (lo, hi)) in enumerate(zip(base.instances, boxes)):
+        i2 = replace(inst, lo=(lo[0], lo[1], 0.0), hi=(hi[0], hi[1], 1.0))
+        x, y = i2.mesh()
+        cx, cy = 0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1])
+        psis.append(W._normalise(i2, np.exp(-((x - 0.3 * cx) ** 2 + 1.5 * (y - 0.3 * cy) ** 2) / 2).astype(complex)))
+        insts.append(i2)
+    w = replace(base, instances=insts, psi0=psis)
+    _, _, got = run_gpu(pkg, w, dtype, use_graph=True)
+    for k, inst in enumerate(insts):
+        ref = oracle.evolve(inst, psis[k], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
+        err = W.rel_l2(got[k], ref)
+        say("box %s %s rel_l2 %.2e" % (boxes[k], dtype, err))
+        assert err < TOL[dtype]
