@@ -342,3 +342,24 @@ def test_c64_error_grows_like_sqrt_n(pkg):
         % (", ".join("%.2e" % e for e in errs), slope, drift))
     assert slope < 0.9 and errs[2] < 5e-5
     assert drift < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_same_size_instances_with_different_boxes(pkg, dtype):
+    """Eight N = 256 instances share one resident workgroup; each has its own
+    box, mass, trap and nonlinearity."""
+    base = W.batch_1d(n_inst=8, sizes=(256,), nsteps=30, seed=29)
+    rng = np.random.default_rng(29)
+    insts, psis = [], []
+    for inst in base.instances:
+        lo = float(rng.uniform(-12.0, -4.0))
+        hi = lo + float(rng.uniform(10.0, 20.0))
+        i2 = replace(inst, lo=(lo, 0.0, 0.0), hi=(hi, 1.0, 1.0), mu=float(rng.uniform(0.7, 1.5)))
+        x = i2.axis(0)
+        psis.append(W._normalise(i2, np.exp(-(x - 0.5 * (lo + hi)) ** 2 / 2).astype(complex)))
+        insts.append(i2)
+    w = replace(base, instances=insts, psi0=psis)
+    _, _, got = run_gpu(pkg, w, dtype)
+    for k, inst in enumerate(insts):
+        ref = oracle.evolve(inst, psis[k], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
+        assert W.rel_l2(got[k], ref) < (1e-11 if dtype == "c128" else 5e-5), k
