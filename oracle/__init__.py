@@ -33,6 +33,18 @@ Parity status per function (the pins live in ``tests/test_oracle_*.py``):
                   breathing mode (which fixes the nonlinear coefficient)
   evolve(vi=...)  pinned: equals the factor form; a linear potential's
                   shifted ground state (closed form)
+  sigma(t) in B   pinned: on a one-point grid the step is the ODE
+                  i u' = (eps V_I + sigma(t)|u|^2) u, and its phase equals the
+                  stage-time quadrature of Table "algorithm" written out from
+                  the printed Table tab.1 values, converging to the closed-form
+                  integral at orders 2 (leapfrog), 4 (SRKN6_4), >= 6 (NI4, NI5);
+                  time reversibility and orders 2 / 4 with time-dependent
+                  sigma(t) (sine and pulse); sigma frozen at t_n, built in the
+                  test, fails both
+  V_I factors     pinned: potential energy and the B flow of the factor form
+                  (c0 + c2 x^2 + c4 x^4) exp(-x^2/gs) cos(k x + phi) against
+                  NumPy evaluations of the formula, with gs, c4 and the other
+                  coefficients varied
   norm, energy    pinned: closed-form Gaussian values
   scheme_coefficients
                   pinned: sums, palindromes and quadrature moments of the

@@ -745,7 +745,7 @@ static int grid_init(grid_t *G, int ndim, const int *n, const double *lo, const 
         double L = G->dx[j] * G->n[j];
         for (int i = 0; i < G->n[j]; ++i) {
             double x = (j < ndim) ? G->lo[j] + i * G->dx[j] : 0.0;
-            int q = (i < G->n[j] / 2) ? i : i - G->n[j];
+            int q = (2 * i < G->n[j]) ? i : i - G->n[j];
             double k = (j < ndim) ? 2.0 * ORC_PI / L * q : 0.0;
             G->x2h[off + i] = 0.5 * x * x;
             G->k2h[off + i] = 0.5 * k * k;
@@ -834,7 +834,7 @@ static void point_coords(const grid_t *G, long idx, double *x, double *k)
         if (x) x[j] = G->lo[j] + i * G->dx[j];
         if (k) {
             double L = G->dx[j] * G->n[j];
-            long q = (i < G->n[j] / 2) ? i : i - G->n[j];
+            long q = (2 * i < G->n[j]) ? i : i - G->n[j];
             k[j] = 2.0 * ORC_PI / L * (double)q;
         }
     }

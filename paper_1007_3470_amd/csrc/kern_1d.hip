@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kThreads1D, (P <= 8 ? 2 : 1)) void hf1d_kernel(cons
 #pragma unroll
             for (int c = 0; c < P; ++c) {
                 int q = tl + c * T;
-                int sq = q - ((q >= (N >> 1)) ? N : 0);
+                int sq = q - ((2 * q >= N) ? N : 0);
                 double k = ks * (double)sq;
                 double2 f = cis_neg_tab(g * (0.5 * k * k), ctab);
                 u[c] = cmul(u[c], make_double2(f.x * invN, f.y * invN));
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kThreads1D) void kin1d_kernel(const Item1D *__restr
 #pragma unroll
     for (int c = 0; c < P; ++c) {
         int q = tl + c * T;
-        int sq = q - ((q >= (N >> 1)) ? N : 0);
+        int sq = q - ((2 * q >= N) ? N : 0);
         double k = I.kscale[0] * (double)sq;
         double v = k * k * fma(u[c].x, u[c].x, u[c].y * u[c].y);
         double t = s + v;

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kThreadsND) void kin_nd_kernel(const InstDev *__res
 #pragma unroll
         for (int c = 0; c < P; ++c) {
             int q = tl + c * T;
-            int sq = q - ((q >= (nj >> 1)) ? nj : 0);
+            int sq = q - ((2 * q >= nj) ? nj : 0);
             double k = I.kscale[axis] * (double)sq;
             double v = k * k * fma(u[c].x, u[c].x, u[c].y * u[c].y) / (double)nj;
             double t = s + v;

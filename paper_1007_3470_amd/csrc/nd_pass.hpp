@@ -230,7 +230,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
                 if constexpr (KIND == kPassSep) {
                     const double gk = r.g[axis], ks = I.kscale[axis];
                     for (int q = threadIdx.x; q < nj; q += blockDim.x) {
-                        int sq = q - ((q >= (nj >> 1)) ? nj : 0);
+                        int sq = q - ((2 * q >= nj) ? nj : 0);
                         double k = ks * (double)sq;
                         double2 f = cis_neg_tab(gk * (0.5 * k * k), ctab);
                         kfl[q] = make_double2(f.x * invN, f.y * invN);
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
             for (int j = 0; j < sh.ndim; ++j) {
                 if (j != axis) {
                     const int i = (base >> shift) & (sh.n[j] - 1);
-                    const int sq = i - ((i >= (sh.n[j] >> 1)) ? sh.n[j] : 0);
+                    const int sq = i - ((2 * i >= sh.n[j]) ? sh.n[j] : 0);
                     ko[j] = I.kscale[j] * (double)sq;
                     scale *= 1.0 / (double)sh.n[j];
                 }
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
 #pragma unroll
             for (int c = 0; c < P; ++c) {
                 const int q = tl + c * T;
-                const int sq = q - ((q >= (nj >> 1)) ? nj : 0);
+                const int sq = q - ((2 * q >= nj) ? nj : 0);
                 const double k = ksa * (double)sq;
                 const double2 f = cis_neg_tab(fma(k, fma(gaa, 0.5 * k, c1), c0), ctab);
                 u[c] = cmul(u[c], make_double2(f.x * scale, f.y * scale));

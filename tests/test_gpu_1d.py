@@ -363,3 +363,39 @@ def test_same_size_instances_with_different_boxes(pkg, dtype):
     for k, inst in enumerate(insts):
         ref = oracle.evolve(inst, psis[k], w.scheme, w.ho_rule, w.dt, w.t0, w.nsteps)
         assert W.rel_l2(got[k], ref) < (1e-11 if dtype == "c128" else 5e-5), k
+
+
+# ---------------------------------------------------------------------------
+# one-point grid: the step reduces to the ODE i u' = (eps V_I + sigma(t)|u|^2) u
+# (x = 0, k = 0), whose split solution turns the phase by the quadrature
+# h sum_i b_i (eps V_I + sigma(tau_i) |u|^2) at the stage times of Table
+# "algorithm" -- checked without the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 2e-7)])
+@pytest.mark.parametrize("scheme", ["leapfrog", "ni5_84"])
+def test_one_point_grid_stage_time_quadrature(pkg, dtype, tol, scheme):
+    import torch
+    sigs = [(5.0, 0.5, 3.0, 0.2, 0), (4.0, 0.8, 2.5, 0.9, 2)]
+    insts = [W.Instance(1, (1, 1, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0),
+                        omega=((1.3, 0.2, 2.0, 0.1), W.CONST_OMEGA, W.CONST_OMEGA), sigma=s, eps=0.3,
+                        vfac=((2.0, 0.0, 0.0, 0.0, 0.0, 0.0), W.NO_V, W.NO_V)) for s in sigs]
+    u0 = np.array([0.9 + 1.2j])
+    t0, h, n = 0.3, 0.05, 24
+    plan = pkg.Plan(insts, scheme, "cf4", dtype, h)
+    buf = plan.pack([u0, u0])
+    plan.evolve(buf, t0, n)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    got = plan.unpack(buf)
+    a, b = pkg.scheme_preset(scheme)
+    c = np.concatenate([[0.0], np.cumsum(a)])
+    for k, s in enumerate(sigs):
+        v0, amp, fr, ph, form = s
+        sig = (lambda t: v0 * (1 + amp * t / math.cosh(fr * (t - ph)) ** 2)) if form == 2 else \
+            (lambda t: v0 * (1 + amp * math.sin(fr * t + ph)))
+        phase = sum(h * b[i] * (0.6 + sig(t0 + j * h + h * c[i]) * 2.25)
+                    for j in range(n) for i in range(len(b)))
+        ex = u0[0] * np.exp(-1j * phase)
+        err = abs(got[k][0] - ex) / abs(ex)
+        say("one-point %s %s sigma form %d: %.3e" % (scheme, dtype, form, err))
+        assert err < tol, (k, err)
