@@ -64,7 +64,12 @@
  *                  2: v(t)   = v0 (1 + amp t sech^2(freq (t - phase)))  (the
  *                     short pulse of the second example of Sec. 4.2)
  *
- * Build: gcc -O2 -std=c99 -ffp-contract=off -fPIC -shared -lm
+ * Threads: evolve and energy take a thread count.  The loops they split
+ * (pencils of an axis transform, grid points of a pointwise flow) compute
+ * every element exactly as one thread would, so the result is bitwise the
+ * same for any count; reductions (norm, energy sums) stay sequential.
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fopenmp -fPIC -shared -lm
  */
 #include <math.h>
 #include <stdlib.h>
@@ -205,8 +210,8 @@ static void fft_contig(int n, double *z, int sign, const double *tw)
 
 /* FFT along one axis of a row-major d-D array (x fastest).  n[0] is the x
  * extent, n[1] y, n[2] z.  Each pencil is copied out, transformed, copied
- * back. */
-static int fft_axis(const int n[3], int axis, double *z, int sign)
+ * back; the pencils are shared out over nt threads. */
+static int fft_axis(const int n[3], int axis, double *z, int sign, int nt)
 {
     int len = n[axis];
     if (len <= 1) return ORC_OK;
@@ -215,29 +220,39 @@ static int fft_axis(const int n[3], int axis, double *z, int sign)
     long total = (long)n[0] * n[1] * n[2];
     long npencil = total / len;
     double *tw = make_twiddles(len);
-    double *buf = (double *)malloc(sizeof(double) * 2 * len);
-    if (!tw || !buf) { free(tw); free(buf); return ORC_ENOMEM; }
-    for (long pidx = 0; pidx < npencil; ++pidx) {
-        /* pencil start: split pidx into (outer, inner) around the axis */
-        long inner = pidx % stride, outer = pidx / stride;
-        long base = outer * stride * len + inner;
-        for (int i = 0; i < len; ++i) {
-            buf[2 * i] = z[2 * (base + i * stride)];
-            buf[2 * i + 1] = z[2 * (base + i * stride) + 1];
+    if (!tw) return ORC_ENOMEM;
+    int rc = ORC_OK;
+#pragma omp parallel num_threads(nt) if (nt > 1)
+    {
+        double *buf = (double *)malloc(sizeof(double) * 2 * len);
+        if (!buf) {
+#pragma omp atomic write
+            rc = ORC_ENOMEM;
         }
-        fft_contig(len, buf, sign, tw);
-        for (int i = 0; i < len; ++i) {
-            z[2 * (base + i * stride)] = buf[2 * i];
-            z[2 * (base + i * stride) + 1] = buf[2 * i + 1];
+#pragma omp for schedule(static)
+        for (long pidx = 0; pidx < npencil; ++pidx) {
+            if (!buf) continue;
+            /* pencil start: split pidx into (outer, inner) around the axis */
+            long inner = pidx % stride, outer = pidx / stride;
+            long base = outer * stride * len + inner;
+            for (int i = 0; i < len; ++i) {
+                buf[2 * i] = z[2 * (base + i * stride)];
+                buf[2 * i + 1] = z[2 * (base + i * stride) + 1];
+            }
+            fft_contig(len, buf, sign, tw);
+            for (int i = 0; i < len; ++i) {
+                z[2 * (base + i * stride)] = buf[2 * i];
+                z[2 * (base + i * stride) + 1] = buf[2 * i + 1];
+            }
         }
+        free(buf);
     }
     free(tw);
-    free(buf);
-    return ORC_OK;
+    return rc;
 }
 
 /* d-D FFT = 1-D FFT along every axis. */
-int orc_fftn(int ndim, const int *n_in, double *z, int sign)
+static int fftn_nt(int ndim, const int *n_in, double *z, int sign, int nt)
 {
     int n[3] = {1, 1, 1};
     if (ndim < 1 || ndim > 3) return ORC_EINVAL;
@@ -246,10 +261,15 @@ int orc_fftn(int ndim, const int *n_in, double *z, int sign)
         n[j] = n_in[j];
     }
     for (int j = 0; j < ndim; ++j) {
-        int rc = fft_axis(n, j, z, sign);
+        int rc = fft_axis(n, j, z, sign, nt);
         if (rc) return rc;
     }
     return ORC_OK;
+}
+
+int orc_fftn(int ndim, const int *n_in, double *z, int sign)
+{
+    return fftn_nt(ndim, n_in, z, sign, 1);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -708,6 +728,7 @@ typedef struct {
     double *vi;   /* eps * V_I at every grid point */
     double *x2h;  /* per-axis x_j^2 / 2 tables, concatenated */
     double *k2h;  /* per-axis k_j^2 / 2 tables, concatenated */
+    int nt;       /* threads for the pencil and point loops */
 } grid_t;
 
 static long axis_index(const grid_t *G, long idx, int axis)
@@ -720,11 +741,12 @@ static long axis_index(const grid_t *G, long idx, int axis)
 /* vi_in: eps V_I at every point (row-major, x fastest), or NULL for the
  * separable factor form of the parameter block. */
 static int grid_init(grid_t *G, int ndim, const int *n, const double *lo, const double *hi,
-                     const double *par, const double *vi_in)
+                     const double *par, const double *vi_in, int nt)
 {
     memset(G, 0, sizeof(*G));
-    if (ndim < 1 || ndim > 3) return ORC_EINVAL;
+    if (ndim < 1 || ndim > 3 || nt < 1) return ORC_EINVAL;
     G->ndim = ndim;
+    G->nt = nt;
     G->par = par;
     G->total = 1;
     int off = 0;
@@ -753,6 +775,7 @@ static int grid_init(grid_t *G, int ndim, const int *n, const double *lo, const 
         off += G->n[j];
     }
     double eps = par_eps(par);
+#pragma omp parallel for schedule(static) num_threads(nt) if (nt > 1)
     for (long idx = 0; idx < G->total; ++idx) {
         double v = 1.0;
         for (int j = 0; j < ndim; ++j) {
@@ -794,6 +817,7 @@ static void apply_B(const grid_t *G, double *u, double dt, double w, double tau)
 {
     if (w == 0.0) return;
     double sig = par_sigma(G->par, tau);
+#pragma omp parallel for schedule(static) num_threads(G->nt) if (G->nt > 1)
     for (long idx = 0; idx < G->total; ++idx) {
         double a2 = u[2 * idx] * u[2 * idx] + u[2 * idx + 1] * u[2 * idx + 1];
         mul_phase(u + 2 * idx, dt * w * (G->vi[idx] + sig * a2));
@@ -803,6 +827,7 @@ static void apply_B(const grid_t *G, double *u, double dt, double w, double tau)
 /* Kick K(c): u <- exp(-i sum_j c_j x_j^2 / 2) u. */
 static void apply_K(const grid_t *G, double *u, const double *c)
 {
+#pragma omp parallel for schedule(static) num_threads(G->nt) if (G->nt > 1)
     for (long idx = 0; idx < G->total; ++idx) {
         double th = 0.0;
         for (int j = 0; j < G->ndim; ++j)
@@ -815,15 +840,16 @@ static void apply_K(const grid_t *G, double *u, const double *c)
  * (Eq. GP1ODE_T and its solution). */
 static int apply_D(const grid_t *G, double *u, const double *g)
 {
-    int rc = orc_fftn(G->ndim, G->n, u, -1);
+    int rc = fftn_nt(G->ndim, G->n, u, -1, G->nt);
     if (rc) return rc;
+#pragma omp parallel for schedule(static) num_threads(G->nt) if (G->nt > 1)
     for (long idx = 0; idx < G->total; ++idx) {
         double th = 0.0;
         for (int j = 0; j < G->ndim; ++j)
             th += g[j] * axis_table(G, G->k2h, j)[axis_index(G, idx, j)];
         mul_phase(u + 2 * idx, th);
     }
-    return orc_fftn(G->ndim, G->n, u, +1);
+    return fftn_nt(G->ndim, G->n, u, +1, G->nt);
 }
 
 /* Coordinates (or wavenumbers) of grid point idx along every axis. */
@@ -851,6 +877,7 @@ static double quad_form(int d, const double *C, const double *v)
 /* Chirp with a symmetric matrix: u <- exp(-i x^T C x / 2) u. */
 static void apply_K_full(const grid_t *G, double *u, const double *C)
 {
+#pragma omp parallel for schedule(static) num_threads(G->nt) if (G->nt > 1)
     for (long idx = 0; idx < G->total; ++idx) {
         double x[3];
         point_coords(G, idx, x, NULL);
@@ -861,14 +888,15 @@ static void apply_K_full(const grid_t *G, double *u, const double *C)
 /* Drift with a symmetric matrix: FFT, u^ <- exp(-i k^T G k / 2) u^, inverse FFT. */
 static int apply_D_full(const grid_t *G, double *u, const double *Gm)
 {
-    int rc = orc_fftn(G->ndim, G->n, u, -1);
+    int rc = fftn_nt(G->ndim, G->n, u, -1, G->nt);
     if (rc) return rc;
+#pragma omp parallel for schedule(static) num_threads(G->nt) if (G->nt > 1)
     for (long idx = 0; idx < G->total; ++idx) {
         double k[3];
         point_coords(G, idx, NULL, k);
         mul_phase(u + 2 * idx, quad_form(G->ndim, Gm, k));
     }
-    return orc_fftn(G->ndim, G->n, u, +1);
+    return fftn_nt(G->ndim, G->n, u, +1, G->nt);
 }
 
 /* B flow of the Fourier split (Eq. FourierSplit) frozen at tau: the harmonic
@@ -882,6 +910,7 @@ static void apply_B_fsplit(const grid_t *G, double *u, double dt, double w, doub
     for (int j = 0; j < G->ndim; ++j) {
         q[j] = mu * par_omega_sq(G->par, j, tau);
     }
+#pragma omp parallel for schedule(static) num_threads(G->nt) if (G->nt > 1)
     for (long idx = 0; idx < G->total; ++idx) {
         double harm = 0.0;
         for (int j = 0; j < G->ndim; ++j)
@@ -961,15 +990,15 @@ static int step_once(const grid_t *G, double *u, int m, const double *a, const d
     return ORC_OK;
 }
 
-/* Public: evolve one instance nsteps steps from t0.  psi is interleaved
- * complex (re, im) in row-major order with x fastest. */
+/* Public: evolve one instance nsteps steps from t0 on nthreads threads.  psi
+ * is interleaved complex (re, im) in row-major order with x fastest. */
 int orc_evolve(int ndim, const int *n, const double *lo, const double *hi, const double *par,
                int m, const double *a, const double *b, int rule, int q, double dt, double t0,
-               long nsteps, const double *vi, double *psi)
+               long nsteps, const double *vi, double *psi, int nthreads)
 {
     if (m < 1 || nsteps < 0) return ORC_EINVAL;
     grid_t G;
-    int rc = grid_init(&G, ndim, n, lo, hi, par, vi);
+    int rc = grid_init(&G, ndim, n, lo, hi, par, vi, nthreads);
     if (rc) { grid_free(&G); return rc; }
     for (long s = 0; s < nsteps && rc == ORC_OK; ++s)
         rc = step_once(&G, psi, m, a, b, rule, q, dt, t0 + (double)s * dt);
@@ -1016,17 +1045,17 @@ int orc_norm(int ndim, const int *n, const double *lo, const double *hi, const d
  *   V = sum_j mu omega_j(t)^2 x_j^2 / 2 + eps V_I(x).
  * out[0..3] = total, kinetic, potential, interaction. */
 int orc_energy(int ndim, const int *n, const double *lo, const double *hi, const double *par,
-               double t, const double *vi, const double *psi, double *out)
+               double t, const double *vi, const double *psi, double *out, int nthreads)
 {
     grid_t G;
-    int rc = grid_init(&G, ndim, n, lo, hi, par, vi);
+    int rc = grid_init(&G, ndim, n, lo, hi, par, vi, nthreads);
     if (rc) { grid_free(&G); return rc; }
     double cell = 1.0;
     for (int j = 0; j < ndim; ++j) cell *= G.dx[j];
     double *uh = (double *)malloc(sizeof(double) * 2 * G.total);
     if (!uh) { grid_free(&G); return ORC_ENOMEM; }
     memcpy(uh, psi, sizeof(double) * 2 * G.total);
-    rc = orc_fftn(ndim, G.n, uh, -1);
+    rc = fftn_nt(ndim, G.n, uh, -1, G.nt);
     if (rc) { free(uh); grid_free(&G); return rc; }
     double mu = par_mu(par), sig = par_sigma(par, t);
     ksum_t kin = {0, 0}, pot = {0, 0}, inter = {0, 0};
@@ -1069,7 +1098,7 @@ int orc_drift(int ndim, const int *n, const double *lo, const double *hi, const 
     par[0] = 1.0;
     for (int j = 0; j < 3; ++j) par[18 + 6 * j] = 1.0;
     grid_t G;
-    int rc = grid_init(&G, ndim, n, lo, hi, par, NULL);
+    int rc = grid_init(&G, ndim, n, lo, hi, par, NULL, 1);
     if (rc == ORC_OK) rc = apply_D(&G, psi, g);
     grid_free(&G);
     return rc;
