@@ -173,6 +173,12 @@ typedef struct {
                               FFT (by default separable passes along axes of
                               128 .. 1024 points run fixed-shape instances;
                               both give the same bits) */
+    int chunk_steps;       /* most steps per coefficient chunk (0 = as many as
+                              256 MB of per-stage records hold, at most 16384);
+                              a smaller value bounds the plan's record table.
+                              The merged phases carry across chunk boundaries,
+                              so results do not depend on it (bitwise for
+                              FP64).  Negative: INVALID_ARG */
 } hfgpe_options;
 
 typedef struct hfgpe_plan hfgpe_plan;

@@ -190,6 +190,20 @@ __host__ __device__ inline Fge fge_fsplit(double mu, double tau)
     return r;
 }
 
+// The rule as a compile-time constant (the coefficient kernel is instantiated
+// per rule, so no other rule's code shares its register allocation).
+template <int RULE, class Om>
+__host__ __device__ inline Fge fge_stage_t(double mu, const Om &om, double t0, double tau, int substeps)
+{
+    if constexpr (RULE == 0) return fge_exact(mu, tf_value(om, t0), tau);
+    if constexpr (RULE == 1) return fge_cf4(mu, om, t0, tau);
+    if constexpr (RULE == 2) return fge_magnus6(mu, om, t0, tau);
+    if constexpr (RULE == 3) return fge_fsplit(mu, tau);
+    if constexpr (RULE == 4) return fge_fundamental(mu, om, t0, tau, substeps);
+    Fge r{0.0, 0.0, 0.0, -1};
+    return r;
+}
+
 template <class Om>
 __host__ __device__ inline Fge fge_stage(int rule, double mu, const Om &om, double t0, double tau, int substeps)
 {

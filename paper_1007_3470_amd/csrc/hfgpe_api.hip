@@ -760,6 +760,7 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
     *out = nullptr;
     if (n_inst < 0 || (n_inst > 0 && (!grids || !params))) return HFGPE_E_INVALID_ARG;
     if (dtype != HFGPE_C64 && dtype != HFGPE_C128) return HFGPE_E_INVALID_ARG;
+    if (opts && opts->chunk_steps < 0) return HFGPE_E_INVALID_ARG;
     if (!std::isfinite(dt) || dt == 0.0) return HFGPE_E_INVALID_ARG;
     int nd = (n_inst > 0) ? grids[0].ndim : 1;
     if (nd < 1 || nd > 3) return HFGPE_E_INVALID_ARG;
@@ -859,6 +860,7 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
     P->m_eff = coupled ? coupled_stages(S) : S.m;
     size_t per_step = (size_t)n_inst * P->m_eff * (sizeof(Rec) + (coupled ? sizeof(RecX) : 0));
     P->rec_steps_cap = (int)std::max<size_t>(1, std::min<size_t>(kRecBudgetBytes / per_step, kRecStepsMax));
+    if (P->opts.chunk_steps > 0) P->rec_steps_cap = std::min(P->rec_steps_cap, P->opts.chunk_steps);
 
 #define ALLOC_TRY(ptr, bytes)                                      \
     do {                                                           \
@@ -1022,6 +1024,8 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
         C.k_steps = k;
         C.nsteps_total = nsteps;
         C.err = P->d_err;
+        C.rule = P->scheme.rule;
+        C.ndim = P->ndim;
         C.stream = P->stream;
         if (host_records) {
             // the staging buffer is reused: wait for the previous chunk's copy

@@ -26,78 +26,95 @@ __device__ __forceinline__ void raise_err(int *err, int code)
     if (code != 0) atomicCAS(err, 0, code);
 }
 
-__global__ void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
-                             const SchemeDev *__restrict__ sch, Rec *__restrict__ rec,
-                             Rec *__restrict__ rec_open, double t0, double dt, int64_t step0,
-                             int k_steps, int64_t nsteps_total, int *err)
+// One instantiation per (HO rule, dimension): the stage loop over axes
+// unrolls and the per-axis coefficients stay in registers.
+template <int RULE, int ND>
+__global__ __launch_bounds__(128) void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
+                                                    const SchemeDev *__restrict__ sch, Rec *__restrict__ rec,
+                                                    Rec *__restrict__ rec_open, double t0, double dt,
+                                                    int64_t step0, int k_steps, int64_t nsteps_total, int *err)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)n_inst * k_steps) return;
     const int inst = (int)(idx / k_steps);
     const int s = (int)(idx % k_steps);
     const InstDev &I = insts[inst];
-    const int m = sch->m, rule = sch->rule, nd = I.ndim;
+    const int m = sch->m, substeps = sch->substeps;
+    const double mu = I.mu;
     const int64_t n = step0 + s;
     const double tn = t0 + (double)n * dt;
     const double tn1 = t0 + (double)(n + 1) * dt;
     const bool last = (n == nsteps_total - 1);
+    int status = 0;
 
-    double fprev[3];
     Rec *out = rec + ((size_t)inst * k_steps + s) * m;
-    Fge cur[3];
-    for (int j = 0; j < nd; ++j) {
-        cur[j] = fge_stage(rule, I.mu, I.om[j], tn, dt * sch->a[0], sch->substeps);
-        raise_err(err, cur[j].status);
+    Fge cur[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        cur[j] = fge_stage_t<RULE>(mu, I.om[j], tn, dt * sch->a[0], substeps);
+        status = status ? status : cur[j].status;
     }
     if (n == 0) {
         Rec o;
-        for (int j = 0; j < 3; ++j) {
-            o.g[j] = 0.0;
-            o.chi[j] = (j < nd) ? cur[j].e : 0.0;
-        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) { o.g[j] = 0.0; o.chi[j] = 0.0; }
+#pragma unroll
+        for (int j = 0; j < ND; ++j) o.chi[j] = cur[j].e;
         o.w = dt * sch->b[0];
         o.s = o.w * tf_value(I.sig, tn);
-        if (rule == 3)
-            for (int j = 0; j < nd; ++j) o.chi[j] += o.w * I.mu * tf_square(I.om[j], tn);
+        if constexpr (RULE == 3) {
+#pragma unroll
+            for (int j = 0; j < ND; ++j) o.chi[j] += o.w * mu * tf_square(I.om[j], tn);
+        }
         rec_open[inst] = o;
     }
     for (int i = 0; i < m; ++i) {
         Rec r;
+        double fprev[ND];
+#pragma unroll
         for (int j = 0; j < 3; ++j) { r.g[j] = 0.0; r.chi[j] = 0.0; }
-        for (int j = 0; j < nd; ++j) {
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
             r.g[j] = cur[j].g;
             fprev[j] = cur[j].f;
         }
         double tau_next;
         if (i < m - 1) {
             tau_next = tn + dt * sch->cum[i + 1];
-            for (int j = 0; j < nd; ++j) {
-                cur[j] = fge_stage(rule, I.mu, I.om[j], tau_next, dt * sch->a[i + 1], sch->substeps);
-                raise_err(err, cur[j].status);
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                cur[j] = fge_stage_t<RULE>(mu, I.om[j], tau_next, dt * sch->a[i + 1], substeps);
+                status = status ? status : cur[j].status;
                 r.chi[j] = fprev[j] + cur[j].e;
             }
             r.w = dt * sch->b[i + 1];
         } else if (!last) {
             tau_next = tn1;
-            for (int j = 0; j < nd; ++j) {
-                Fge q = fge_stage(rule, I.mu, I.om[j], tn1, dt * sch->a[0], sch->substeps);
-                raise_err(err, q.status);
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                Fge q = fge_stage_t<RULE>(mu, I.om[j], tn1, dt * sch->a[0], substeps);
+                status = status ? status : q.status;
                 r.chi[j] = fprev[j] + q.e;
             }
             r.w = dt * (sch->b[m] + sch->b[0]);
         } else {
             tau_next = tn1;
-            for (int j = 0; j < nd; ++j) r.chi[j] = fprev[j];
+#pragma unroll
+            for (int j = 0; j < ND; ++j) r.chi[j] = fprev[j];
             r.w = dt * sch->b[m];
         }
         r.s = r.w * tf_value(I.sig, tau_next);
-        if (rule == 3)  // Fourier split: the harmonic potential is part of B
-            for (int j = 0; j < nd; ++j) r.chi[j] += r.w * I.mu * tf_square(I.om[j], tau_next);
+        if constexpr (RULE == 3) {  // Fourier split: the harmonic potential is part of B
+#pragma unroll
+            for (int j = 0; j < ND; ++j) r.chi[j] += r.w * mu * tf_square(I.om[j], tau_next);
+        }
         bool finite = isfinite(r.w) && isfinite(r.s);
+#pragma unroll
         for (int j = 0; j < 3; ++j) finite = finite && isfinite(r.g[j]) && isfinite(r.chi[j]);
-        if (!finite) raise_err(err, -7);
+        if (!finite && !status) status = -7;
         out[i] = r;
     }
+    raise_err(err, status);
 }
 
 // Coupled trap (non-diagonal W, d >= 2): one record per effective stage (two
@@ -202,6 +219,37 @@ __global__ void coeff_coupled_kernel(const InstDev *__restrict__ insts, int n_in
     }
 }
 
+template <int RULE, int ND>
+static hipError_t launch_coeff_t(const LaunchCoeff &L, unsigned grid, int bs)
+{
+    hipLaunchKernelGGL((coeff_kernel<RULE, ND>), dim3(grid), dim3(bs), 0, L.stream, L.insts, L.n_inst, L.scheme,
+                       L.rec, L.rec_open, L.t0, L.dt, L.step0, L.k_steps, L.nsteps_total, L.err);
+    return hipGetLastError();
+}
+
+template <int RULE>
+static hipError_t launch_coeff_nd(const LaunchCoeff &L, unsigned grid, int bs)
+{
+    switch (L.ndim) {
+    case 1: return launch_coeff_t<RULE, 1>(L, grid, bs);
+    case 2: return launch_coeff_t<RULE, 2>(L, grid, bs);
+    case 3: return launch_coeff_t<RULE, 3>(L, grid, bs);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t launch_coeff_rule(const LaunchCoeff &L, unsigned grid, int bs)
+{
+    switch (L.rule) {
+    case 0: return launch_coeff_nd<0>(L, grid, bs);
+    case 1: return launch_coeff_nd<1>(L, grid, bs);
+    case 2: return launch_coeff_nd<2>(L, grid, bs);
+    case 3: return launch_coeff_nd<3>(L, grid, bs);
+    case 4: return launch_coeff_nd<4>(L, grid, bs);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_coeff(const LaunchCoeff &L)
 {
     int64_t total = (int64_t)L.n_inst * L.k_steps;
@@ -214,10 +262,7 @@ hipError_t launch_coeff(const LaunchCoeff &L)
                            L.nsteps_total, L.err);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(coeff_kernel, dim3((unsigned)grid), dim3(bs), 0, L.stream, L.insts, L.n_inst,
-                       L.scheme, L.rec, L.rec_open, L.t0, L.dt, L.step0, L.k_steps, L.nsteps_total,
-                       L.err);
-    return hipGetLastError();
+    return launch_coeff_rule(L, (unsigned)grid, bs);
 }
 
 }  // namespace hfgpe

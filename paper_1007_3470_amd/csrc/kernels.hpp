@@ -21,6 +21,8 @@ struct LaunchCoeff {
     int k_steps;              // steps in this chunk
     int64_t nsteps_total;     // steps of the whole evolve call
     int *err;                 // device error word
+    int rule;                 // HO rule of the scheme (selects the kernel instance)
+    int ndim;
     hipStream_t stream;
 };
 hipError_t launch_coeff(const LaunchCoeff &L);
