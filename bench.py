@@ -89,34 +89,52 @@ def timed_evolve(pkg, torch, w, dtype, K, warmup, **kw):
     return plan, buf, wall, gpu_ms, step_ms, coeff_ms, launches
 
 
-def nd_workload(pkg, torch, W, w, sc_bytes):
-    """Secondary measurement: a d-D workload at full size, c64 and c128, graph
-    replay; per-pass HBM roofline from the library's HIP events."""
+def nd_passes_per_step(pkg, w) -> int:
+    """Axis passes of one d-D step: d per stage for a separable trap; for a
+    coupled trap 2d - 1 per exponential (two per stage under CF4, one
+    otherwise), the Fourier split staying separable."""
+    d = w.instances[0].ndim
+    m = len(pkg.scheme_preset(w.scheme)[0])
+    coupled = any(any(v != 0.0 for v in getattr(i, "wcross", (0.0, 0.0, 0.0))) for i in w.instances)
+    if not coupled or w.ho_rule == "fsplit":
+        return m * d
+    return (2 * m if w.ho_rule == "cf4" else m) * (2 * d - 1)
+
+
+def nd_workload(pkg, torch, W, w, reps=5):
+    """Secondary measurement: a d-D workload at full size and length, c64 and
+    c128, steps replayed from hipGraph blocks.  The run is timed with HIP
+    events on the plan's stream, median of `reps` runs from the same input;
+    the per-pass time is that step time over the passes per step (the one
+    opening pass and the coefficient kernel of the run included)."""
     out = {}
     res = {}
+    npass = nd_passes_per_step(pkg, w)
     for dtype, sc in (("c64", 8), ("c128", 16)):
         plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, use_graph=True)
         scratch = plan.pack(w.psi0)
         plan.evolve(scratch, 0.0, 2)
         del scratch
-        buf = plan.pack(w.psi0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan.evolve(buf, 0.0, w.nsteps)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+        stream = torch.cuda.current_stream()
+        runs = []
+        for _ in range(reps):
+            buf = plan.pack(w.psi0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            plan.evolve(buf, 0.0, w.nsteps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            runs.append(e0.elapsed_time(e1) / 1e3)
         res[dtype] = plan.unpack(buf)
-        # per-pass time from a short profiled run without graphs
-        prof = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, profile=True)
-        b2 = prof.pack(w.psi0)
-        prof.evolve(b2, 0.0, 2)
-        prof.profile()
-        prof.evolve(b2, 0.0, 8)
-        kms, _, nl = prof.profile()
-        pass_s = kms / 1e3 / nl
+        run_s = float(np.median(runs))
+        pass_s = run_s / (w.nsteps * npass)
         bw = 2.0 * sc * w.points / pass_s / 1e9
-        out[dtype] = {"value": w.points * w.nsteps / wall, "ms_per_step": wall * 1e3 / w.nsteps,
+        out[dtype] = {"value": w.points * w.nsteps / run_s, "ms_per_step": run_s * 1e3 / w.nsteps,
+                      "runs_s": [round(r, 6) for r in runs], "passes_per_step": npass,
                       "pass_us": pass_s * 1e6, "pass_GBs": bw, "pass_frac_of_hbm_peak": bw / HBM_PEAK_GBS}
+        del plan, buf
+    out["c64_pass_time_over_c128"] = out["c64"]["pass_us"] / out["c128"]["pass_us"]
     out["l2_c64_vs_c128_max"] = max(W.rel_l2(a, b) for a, b in zip(res["c64"], res["c128"]))
     progress("%s done" % w.name)
     out["workload"] = w.notes + ", %s + %s, dt=%g, %d steps" % (w.scheme, w.ho_rule, w.dt, w.nsteps)
@@ -363,7 +381,7 @@ def main(argv=None):
     nd_sets = (("gpe_2d", W.gpe_2d), ("gpe_3d", W.gpe_3d), ("coupled_2d", W.coupled_2d),
                ("coupled_3d", W.coupled_3d))
     if args.nd_only:
-        print(json.dumps({"other_workloads": {name: nd_workload(pkg, torch, W, gen(**nd_kw), 8)
+        print(json.dumps({"other_workloads": {name: nd_workload(pkg, torch, W, gen(**nd_kw))
                                               for name, gen in nd_sets}}), flush=True)
         return 0
     w = W.batch_1d(nsteps=K)
@@ -420,7 +438,7 @@ def main(argv=None):
         "wall_s": {"c64": wall64, "c128": wall128},
     }
     if not args.no_nd:
-        line["other_workloads"] = {name: nd_workload(pkg, torch, W, gen(**nd_kw), 8) for name, gen in nd_sets}
+        line["other_workloads"] = {name: nd_workload(pkg, torch, W, gen(**nd_kw)) for name, gen in nd_sets}
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

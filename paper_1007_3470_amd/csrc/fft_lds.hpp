@@ -172,14 +172,16 @@ struct Fft1D {
     }
 };
 
-// Fixed-shape radix-8 FFT of the resident 1-D kernel: N = 2^LOGN points split
-// over T = N/8 threads (T a multiple of 8), FP64 exchange, one padding element
-// every 8 (as Fft1D with pad = true, istride = 1).  With the shape known at
+// Fixed-shape radix-8 FFT on padded rows: N = 2^LOGN points split over
+// T = N/8 threads (T a multiple of 8), one padding element every 8 (as Fft1D
+// with pad = true, istride = 1).  Xch is the LDS exchange type: double2 for
+// the resident 1-D kernel and the c128 passes, float2 for the c64 d-D passes
+// (arithmetic and twiddles stay FP64 either way).  With the shape known at
 // compile time each LDS address is a per-thread base plus a constant, so the
 // addresses of all passes fold into instruction offsets instead of occupying
 // registers across the step loop.  The padding algebra used below:
 // pad(x + y) = pad(x) + y + (y >> 3) whenever (x mod 8) + (y mod 8) < 8.
-template <int LOGN>
+template <int LOGN, typename Xch = double2>
 struct FftFix8 {
     static constexpr int P = 8, LOGP = 3;
     static constexpr int N = 1 << LOGN;
@@ -192,7 +194,7 @@ struct FftFix8 {
     static constexpr int TP = T + (T >> 3);              // padded stride of the points {t + cT}
     static_assert(kPadShift == 3 && T % 8 == 0 && S >= 2, "fixed-shape FFT: N >= 64");
 
-    double2 *lds;
+    Xch *lds;
     int roff;             // pad(t) + instance row
     int w0off;            // pad(t R0) + instance row
     int woff[S > 2 ? S - 2 : 1];  // pass s write base, s = 1 .. S-2
@@ -200,7 +202,7 @@ struct FftFix8 {
 
     // twtab (optional): exp(-2 pi i q / 2^twlog) for q < 2^twlog, twlog >= LOGN;
     // without it the twiddles are evaluated with sincospi
-    __device__ __forceinline__ void init(int tl, int slot, double2 *lds_, const double2 *__restrict__ twtab = nullptr,
+    __device__ __forceinline__ void init(int tl, int slot, Xch *lds_, const double2 *__restrict__ twtab = nullptr,
                                          int twlog = 0)
     {
         lds = lds_;
@@ -245,13 +247,13 @@ struct FftFix8 {
             for (int r = 0; r < R0; ++r) v[r] = u[b + r * NB];
             Dft<R0, SGN>::run(v);
 #pragma unroll
-            for (int rp = 0; rp < R0; ++rp) lds[w0off + b * BSTR + rp] = v[rp];
+            for (int rp = 0; rp < R0; ++rp) lds[w0off + b * BSTR + rp] = from_d2<Xch>(v[rp]);
         }
 #pragma unroll
         for (int s = 1; s < S; ++s) {
             __syncthreads();
 #pragma unroll
-            for (int c = 0; c < P; ++c) u[c] = lds[roff + c * TP];
+            for (int c = 0; c < P; ++c) u[c] = to_d2(lds[roff + c * TP]);
             __syncthreads();
             const double2 w1 = tw[s - 1][0], w2 = tw[s - 1][1], w4 = tw[s - 1][2];
             const double2 w3 = cmul(w1, w2);
@@ -262,7 +264,7 @@ struct FftFix8 {
             if (s < S - 1) {
                 const int L = 1 << (R0LOG + LOGP * (s - 1));
 #pragma unroll
-                for (int rp = 0; rp < P; ++rp) lds[woff[s - 1] + rp * L + ((rp * L) >> 3)] = u[rp];
+                for (int rp = 0; rp < P; ++rp) lds[woff[s - 1] + rp * L + ((rp * L) >> 3)] = from_d2<Xch>(u[rp]);
             }
         }
     }
@@ -272,8 +274,9 @@ struct FftFix8 {
 // workgroup are interleaved in LDS (point idx of pencil `slot` at idx * G +
 // slot, no padding), a pencil's N = 2^LOGN points are split over T = N/8
 // threads, and the passes and twiddles are those of Fft1D.  As in FftFix8 every
-// LDS address is a per-thread base plus a compile-time constant.
-template <int LOGN, int G>
+// LDS address is a per-thread base plus a compile-time constant, and Xch is
+// the exchange type.
+template <int LOGN, int G, typename Xch = double2>
 struct FftFixS8 {
     static constexpr int P = 8, LOGP = 3;
     static constexpr int N = 1 << LOGN;
@@ -284,13 +287,13 @@ struct FftFixS8 {
     static constexpr int R0 = 1 << R0LOG;
     static_assert(S >= 2 && G >= 1, "fixed-shape strided FFT: N >= 16");
 
-    double2 *lds;
+    Xch *lds;
     int roff;                     // tl G + slot: point tl of the pencil
     int w0off;                    // tl R0 G + slot: pass 0 write base
     int woff[S > 2 ? S - 2 : 1];  // pass s write base, s = 1 .. S-2
     double2 tw[S - 1][3];         // w^1, w^2, w^4 of passes 1 .. S-1
 
-    __device__ __forceinline__ void init(int tl, int slot, double2 *lds_, const double2 *__restrict__ twtab,
+    __device__ __forceinline__ void init(int tl, int slot, Xch *lds_, const double2 *__restrict__ twtab,
                                          int twlog)
     {
         lds = lds_;
@@ -319,13 +322,13 @@ struct FftFixS8 {
             for (int r = 0; r < R0; ++r) v[r] = u[b + r * NB];
             Dft<R0, SGN>::run(v);
 #pragma unroll
-            for (int rp = 0; rp < R0; ++rp) lds[w0off + b * BSTR + rp * G] = v[rp];
+            for (int rp = 0; rp < R0; ++rp) lds[w0off + b * BSTR + rp * G] = from_d2<Xch>(v[rp]);
         }
 #pragma unroll
         for (int s = 1; s < S; ++s) {
             __syncthreads();
 #pragma unroll
-            for (int c = 0; c < P; ++c) u[c] = lds[roff + c * T * G];
+            for (int c = 0; c < P; ++c) u[c] = to_d2(lds[roff + c * T * G]);
             __syncthreads();
             const double2 w1 = tw[s - 1][0], w2 = tw[s - 1][1], w4 = tw[s - 1][2];
             const double2 w3 = cmul(w1, w2);
@@ -336,7 +339,7 @@ struct FftFixS8 {
             if (s < S - 1) {
                 const int L = 1 << (R0LOG + LOGP * (s - 1));
 #pragma unroll
-                for (int rp = 0; rp < P; ++rp) lds[woff[s - 1] + rp * L * G] = u[rp];
+                for (int rp = 0; rp < P; ++rp) lds[woff[s - 1] + rp * L * G] = from_d2<Xch>(u[rp]);
             }
         }
     }

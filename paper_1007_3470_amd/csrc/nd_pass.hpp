@@ -56,17 +56,31 @@ enum { kPassSep = 0, kPassFwd = 1, kPassMid = 2, kPassInv = 3 };
 // FFT of a pass: the runtime-shaped Fft1D (FIX = 0), or for FIX = 2 LOGN + s a
 // fixed-shape radix-8 FFT of 2^LOGN points, on padded rows (s = 0, axis 0) or
 // interleaved pencils (s = 1, strided axes, TPB / (N/8) pencils per group).
-template <int P, int MAXS, int FIX, int TPB, bool = (FIX != 0), bool = ((FIX & 1) != 0)>
+template <typename Xch, int P, int MAXS, int FIX, int TPB, bool = (FIX != 0), bool = ((FIX & 1) != 0)>
 struct NdFft {
-    using type = Fft1D<double2, P, MAXS>;
+    using type = Fft1D<Xch, P, MAXS>;
 };
-template <int P, int MAXS, int FIX, int TPB>
-struct NdFft<P, MAXS, FIX, TPB, true, false> {
-    using type = FftFix8<(FIX >> 1)>;
+template <typename Xch, int P, int MAXS, int FIX, int TPB>
+struct NdFft<Xch, P, MAXS, FIX, TPB, true, false> {
+    using type = FftFix8<(FIX >> 1), Xch>;
 };
-template <int P, int MAXS, int FIX, int TPB>
-struct NdFft<P, MAXS, FIX, TPB, true, true> {
-    using type = FftFixS8<(FIX >> 1), (TPB >> ((FIX >> 1) - 3))>;
+template <typename Xch, int P, int MAXS, int FIX, int TPB>
+struct NdFft<Xch, P, MAXS, FIX, TPB, true, true> {
+    using type = FftFixS8<(FIX >> 1), (TPB >> ((FIX >> 1) - 3)), Xch>;
+};
+
+// LDS exchange type of a pass.  The c64 passes round the state to c64 at
+// every HBM store anyway; exchanging FP32 between the FFT's radix passes adds
+// a few such roundings per pass (arithmetic, twiddles and phase factors stay
+// FP64) and halves the LDS bytes of passes whose time is spent in exchanges.
+// The c128 passes exchange FP64.
+template <typename Store>
+struct NdXch {
+#ifdef HFGPE_ND_XCH64
+    using type = double2;
+#else
+    using type = Store;
+#endif
 };
 
 template <typename Store, int P, int MAXS, int MODE, int TPB, int KIND, int FIX>
@@ -88,7 +102,8 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     constexpr bool FSTRIDED = (FIX & 1) != 0;
     static_assert(FIX == 0 || P == 8, "fixed-shape passes are radix 8");
     constexpr int LDS_ELEMS = (FIX != 0 && FSTRIDED) ? TPB * P : TPB * P + ((TPB * P) >> kPadShift);
-    __shared__ double2 lds[LDS_ELEMS];
+    using Xch = typename NdXch<Store>::type;
+    __shared__ Xch lds[LDS_ELEMS];
     __shared__ CisTable ctab;
     constexpr int kAxisTab = FIX ? (1 << FLOGN) : kMaxAxisND;
     __shared__ double2 kfl[kAxisTab];  // drift factor of every wavenumber of the axis
@@ -112,7 +127,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     const int64_t gpi = npencil >> lg;  // groups per instance
     const int tid = threadIdx.x;
     int slot, tl;
-    typename NdFft<P, MAXS, FIX, TPB>::type fft;
+    typename NdFft<Xch, P, MAXS, FIX, TPB>::type fft;
     if (xaxis) {
         slot = tid >> logT;
         tl = tid & (T - 1);

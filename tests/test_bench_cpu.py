@@ -67,3 +67,19 @@ def test_flops_per_grid_point_step():
 def test_more_than_one_gpu_is_refused(capsys):
     assert bench.main(["--gpus", "2"]) == 2
     assert "one GPU only" in capsys.readouterr().err
+
+
+def test_nd_passes_per_step():
+    """Passes per d-D step, from which the bench derives per-pass times:
+    m d for separable traps, (2d - 1) per exponential for coupled ones (CF4
+    applies two exponentials per stage)."""
+    import bench
+    import paper_1007_3470_amd as pkg
+    import workloads as W
+    assert bench.nd_passes_per_step(pkg, W.gpe_2d(n=16, n_inst=1, nsteps=1)) == 2
+    assert bench.nd_passes_per_step(pkg, W.gpe_3d(n=16, nsteps=1)) == 15
+    assert bench.nd_passes_per_step(pkg, W.coupled_2d(n=16, n_inst=1, nsteps=1)) == 6
+    assert bench.nd_passes_per_step(pkg, W.coupled_3d(n=16, nsteps=1)) == 50
+    assert bench.nd_passes_per_step(pkg, W.coupled_2d(n=16, n_inst=1, nsteps=1, rule="fsplit")) == 2
+    assert bench.nd_passes_per_step(pkg, W.coupled_2d(n=16, n_inst=1, nsteps=1, rule="exact_const",
+                                                      constant=True)) == 3
