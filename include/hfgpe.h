@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 #define HFGPE_VERSION_MAJOR 0
-#define HFGPE_VERSION_MINOR 1
+#define HFGPE_VERSION_MINOR 2
 
 /* Status codes. */
 #define HFGPE_OK 0
@@ -112,6 +112,17 @@ typedef struct {
     int kind; /* hfgpe_tf_kind */
 } hfgpe_tfunc;
 
+/* A time modulation factor m(t) (Sec. 1 lets the quadratic part M(t) and the
+ * perturbation V_I depend on time):
+ *   kind HFGPE_TF_SIN:   m(t) = 1 + amp sin(freq t + phase)
+ *   kind HFGPE_TF_PULSE: m(t) = 1 + amp t / cosh^2(freq (t - phase))
+ *                        (freq non-zero when amp is)
+ * Zero-initialised (amp = 0): m = 1, no time dependence. */
+typedef struct {
+    double amp, freq, phase;
+    int kind; /* HFGPE_TF_SIN or HFGPE_TF_PULSE */
+} hfgpe_tmod;
+
 /* One separable factor of the perturbation V_I:
  *   v(x) = (c0 + c2 x^2 + c4 x^4) * exp(-x^2 / gs) * cos(k x + phi),
  * the Gaussian factor being omitted when gs <= 0.  V_I(x) = prod_j v_j(x_j). */
@@ -128,17 +139,26 @@ typedef struct {
                                kind HFGPE_TF_SIN or HFGPE_TF_PULSE */
     double eps;             /* strength of V_I */
     hfgpe_vfactor v[3];     /* V_I factors; set c0 = 1, rest 0, for "no factor" */
-    double wcross[3];       /* coupled trap (d >= 2): constant off-diagonal entries
+    double wcross[3];       /* coupled trap (d >= 2): off-diagonal entries
                                W_xy, W_xz, W_yz of the squared-frequency matrix W(t)
-                               with W_jj = omega_j(t)^2; the trap is then
-                               (mu/2) x^T W(t) x, the general quadratic potential of
-                               Sec. 1.  Zero-initialise for a diagonal trap.  A plan
+                               with W_jj = omega_j(t)^2, each times its modulation
+                               wmod[k]; the trap is then (mu/2) x^T W(t) x, the
+                               general quadratic potential x^T M(t) x of Sec. 1.
+                               Zero-initialise for a diagonal trap.  A plan
                                whose instances use it must have it on all of them;
-                               rules: EXACT_CONST (omega constant; one drift per
-                               stage), CF4 (applied as its two exponentials: two
-                               drifts per stage) and FSPLIT; W(t) must stay positive
+                               rules: EXACT_CONST (omega and W constant; one drift
+                               per stage), CF4 (W(t) averaged at its Gauss nodes,
+                               cross terms included, and applied as its two
+                               exponentials: two drifts per stage) and FSPLIT
+                               (W(t) at the B times); W(t) must stay positive
                                definite.  The coupled drift k^T G k / 2 is not
                                separable: a stage costs 2d - 1 axis passes. */
+    hfgpe_tmod vmod;        /* time factor of the perturbation:
+                               eps V_I(x, t) = m(t) eps V_I(x), for the factor form
+                               and for a caller's array (hfgpe_set_potential)
+                               alike; evaluated at the B times (Table
+                               "algorithm") */
+    hfgpe_tmod wmod[3];     /* time factors of W_xy, W_xz, W_yz */
 } hfgpe_params;
 
 /* BAB composition of Eq. prod-gen: B(b_0) A(a_0) B(b_1) ... A(a_{m-1}) B(b_m).

@@ -67,7 +67,7 @@ _SRC = os.path.join(_HERE, "hfgpe_oracle.c")
 _SO = os.path.join(_HERE, "libhfgpe_oracle.so")
 _LIB = None
 
-NPAR = 43
+NPAR = 59
 HO_RULES = {"exact_const": 0, "cf4": 1, "magnus6": 2, "fsplit": 3, "fundamental": 4}
 FUNDAMENTAL_DEFAULT_SUBSTEPS = 16
 _ERRORS = {-1: "invalid argument", -2: "singular stage (g = 0)",
@@ -180,6 +180,9 @@ def params_block(inst) -> np.ndarray:
     p[39] = inst.sigma[4] if len(inst.sigma) > 4 else 0
     p[17] = inst.eps
     p[40:43] = getattr(inst, "wcross", (0.0, 0.0, 0.0))
+    p[43:47] = getattr(inst, "vmod", (0.0, 0.0, 0.0, 0))
+    for k, m in enumerate(getattr(inst, "wmod", ((0.0, 0.0, 0.0, 0),) * 3)):
+        p[47 + 4 * k: 51 + 4 * k] = m
     return p
 
 

@@ -53,10 +53,18 @@
  *                           * cos(k x + phi);   V_I = prod_j v_j(x_j)
  *                  (evolve and energy also take eps V_I as an explicit array
  *                  over the grid, which replaces this factor form)
- *   [40..42]       W_xy, W_xz, W_yz: constant off-diagonal entries of the
+ *   [40..42]       W_xy, W_xz, W_yz: off-diagonal entries of the
  *                  squared-frequency matrix W(t) of a coupled trap
  *                  V_HO = (mu/2) x^T W(t) x, W_jj = omega_j(t)^2 (the general
- *                  quadratic potential x^T M x of Sec. 1 with M = mu W / 2)
+ *                  quadratic potential x^T M(t) x of Sec. 1 with M = mu W / 2),
+ *                  each times its modulation [47+4k..50+4k]
+ *   [43..46]       modulation of the perturbation: eps V_I(x, t) =
+ *                  m(t) eps V_I(x) (Sec. 1 lets V_I depend on t)
+ *   [47..58]       modulations of W_xy, W_xz, W_yz
+ *                  a modulation is (amp, freq, phase, form):
+ *                  form 0: m(t) = 1 + amp sin(freq t + phase)
+ *                  form 2: m(t) = 1 + amp t sech^2(freq (t - phase))
+ *                  (all zero: m = 1)
  *   [36+j], [39]   form of omega_j(t), sigma(t):
  *                  0: v(t)   = v0 (1 + amp sin(freq t + phase))
  *                  1: v(t)^2 = v0 (1 + amp sin(freq t + phase))  (the modulated
@@ -75,7 +83,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_NPAR 43
+#define ORC_NPAR 59
 #define ORC_PI 3.14159265358979323846
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ESINGULAR = -2, ORC_EFREQ = -3, ORC_ENOMEM = -4 };
@@ -98,6 +106,16 @@ static double tform(const double *c, int form, double t)
     return c[0] * (1.0 + c[1] * sin(c[2] * t + c[3]));
 }
 
+/* A modulation factor m(t) (parameter block layout above). */
+static double tmod(const double *c, double t)
+{
+    if ((int)c[3] == 2) {
+        double sech = 1.0 / cosh(c[1] * (t - c[2]));
+        return 1.0 + c[0] * t * sech * sech;
+    }
+    return 1.0 + c[0] * sin(c[1] * t + c[2]);
+}
+
 /* omega_j(t)^2 of the trap, Eq. GP1b with a time-dependent frequency. */
 static double par_omega_sq(const double *p, int j, double t)
 {
@@ -114,13 +132,15 @@ static double par_sigma(const double *p, double t)
 
 static double par_eps(const double *p) { return p[17]; }
 
-/* Off-diagonal W_ij of the coupled trap (i != j, axes < 3). */
-static double par_wcross(const double *p, int i, int j)
+/* Time factor of eps V_I at time t. */
+static double par_vmod(const double *p, double t) { return tmod(p + 43, t); }
+
+/* Off-diagonal W_ij(t) of the coupled trap (i != j, axes < 3). */
+static double par_wcross(const double *p, int i, int j, double t)
 {
-    if (i > j) { int t = i; i = j; j = t; }
-    if (i == 0 && j == 1) return p[40];
-    if (i == 0 && j == 2) return p[41];
-    return p[42];
+    if (i > j) { int tt = i; i = j; j = tt; }
+    int k = (i == 0) ? (j == 1 ? 0 : 1) : 2;
+    return p[40 + k] * tmod(p + 47 + 4 * k, t);
 }
 
 static int par_coupled(const double *p, int ndim)
@@ -133,7 +153,7 @@ static void par_wmat(const double *p, int d, double t, double *W)
 {
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j)
-            W[i * d + j] = (i == j) ? par_omega_sq(p, i, t) : par_wcross(p, i, j);
+            W[i * d + j] = (i == j) ? par_omega_sq(p, i, t) : par_wcross(p, i, j, t);
 }
 
 /* One separable factor of the perturbing potential V_I. */
@@ -812,15 +832,15 @@ static void mul_phase(double *z, double theta)
 }
 
 /* B flow frozen at time tau with weight w (Lemma 1; Table "algorithm"):
- * u <- exp(-i dt w (eps V_I + sigma(tau) |u|^2)) u. */
+ * u <- exp(-i dt w (eps V_I(x, tau) + sigma(tau) |u|^2)) u. */
 static void apply_B(const grid_t *G, double *u, double dt, double w, double tau)
 {
     if (w == 0.0) return;
-    double sig = par_sigma(G->par, tau);
+    double sig = par_sigma(G->par, tau), vm = par_vmod(G->par, tau);
 #pragma omp parallel for schedule(static) num_threads(G->nt) if (G->nt > 1)
     for (long idx = 0; idx < G->total; ++idx) {
         double a2 = u[2 * idx] * u[2 * idx] + u[2 * idx + 1] * u[2 * idx + 1];
-        mul_phase(u + 2 * idx, dt * w * (G->vi[idx] + sig * a2));
+        mul_phase(u + 2 * idx, dt * w * (vm * G->vi[idx] + sig * a2));
     }
 }
 
@@ -905,7 +925,7 @@ static int apply_D_full(const grid_t *G, double *u, const double *Gm)
 static void apply_B_fsplit(const grid_t *G, double *u, double dt, double w, double tau)
 {
     if (w == 0.0) return;
-    double sig = par_sigma(G->par, tau), mu = par_mu(G->par);
+    double sig = par_sigma(G->par, tau), mu = par_mu(G->par), vm = par_vmod(G->par, tau);
     double q[3] = {0.0, 0.0, 0.0};
     for (int j = 0; j < G->ndim; ++j) {
         q[j] = mu * par_omega_sq(G->par, j, tau);
@@ -919,10 +939,10 @@ static void apply_B_fsplit(const grid_t *G, double *u, double dt, double w, doub
             double x[3];
             point_coords(G, idx, x, NULL);
             for (int i = 0; i < G->ndim; ++i)
-                for (int j = i + 1; j < G->ndim; ++j) harm += mu * par_wcross(G->par, i, j) * x[i] * x[j];
+                for (int j = i + 1; j < G->ndim; ++j) harm += mu * par_wcross(G->par, i, j, tau) * x[i] * x[j];
         }
         double a2 = u[2 * idx] * u[2 * idx] + u[2 * idx + 1] * u[2 * idx + 1];
-        mul_phase(u + 2 * idx, dt * w * (harm + G->vi[idx] + sig * a2));
+        mul_phase(u + 2 * idx, dt * w * (harm + vm * G->vi[idx] + sig * a2));
     }
 }
 
@@ -1057,7 +1077,7 @@ int orc_energy(int ndim, const int *n, const double *lo, const double *hi, const
     memcpy(uh, psi, sizeof(double) * 2 * G.total);
     rc = fftn_nt(ndim, G.n, uh, -1, G.nt);
     if (rc) { free(uh); grid_free(&G); return rc; }
-    double mu = par_mu(par), sig = par_sigma(par, t);
+    double mu = par_mu(par), sig = par_sigma(par, t), vm = par_vmod(par, t);
     ksum_t kin = {0, 0}, pot = {0, 0}, inter = {0, 0};
     for (long idx = 0; idx < G.total; ++idx) {
         double k2h = 0.0, vh = 0.0;
@@ -1070,12 +1090,12 @@ int orc_energy(int ndim, const int *n, const double *lo, const double *hi, const
             double x[3];
             point_coords(&G, idx, x, NULL);
             for (int i = 0; i < ndim; ++i)
-                for (int j = i + 1; j < ndim; ++j) vh += mu * par_wcross(par, i, j) * x[i] * x[j];
+                for (int j = i + 1; j < ndim; ++j) vh += mu * par_wcross(par, i, j, t) * x[i] * x[j];
         }
         double a2h = uh[2 * idx] * uh[2 * idx] + uh[2 * idx + 1] * uh[2 * idx + 1];
         ksum_add(&kin, k2h / mu * a2h);
         double a2 = psi[2 * idx] * psi[2 * idx] + psi[2 * idx + 1] * psi[2 * idx + 1];
-        ksum_add(&pot, (vh + G.vi[idx]) * a2);
+        ksum_add(&pot, (vh + vm * G.vi[idx]) * a2);
         ksum_add(&inter, 0.5 * sig * a2 * a2);
     }
     out[1] = cell * ksum_val(&kin) / (double)G.total;

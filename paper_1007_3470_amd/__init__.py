@@ -54,9 +54,15 @@ class VFactor(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in ("c0", "c2", "c4", "gs", "k", "phi")]
 
 
+class TMod(ctypes.Structure):
+    _fields_ = [("amp", ctypes.c_double), ("freq", ctypes.c_double), ("phase", ctypes.c_double),
+                ("kind", ctypes.c_int)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("omega", TFunc * 3), ("sigma", TFunc),
-                ("eps", ctypes.c_double), ("v", VFactor * 3), ("wcross", ctypes.c_double * 3)]
+                ("eps", ctypes.c_double), ("v", VFactor * 3), ("wcross", ctypes.c_double * 3),
+                ("vmod", TMod), ("wmod", TMod * 3)]
 
 
 class Scheme(ctypes.Structure):
@@ -209,6 +215,10 @@ def make_params(inst) -> Params:
     p.eps = float(inst.eps)
     for j, v in enumerate(getattr(inst, "wcross", (0.0, 0.0, 0.0))):
         p.wcross[j] = float(v)
+    vm = getattr(inst, "vmod", (0.0, 0.0, 0.0, 0))
+    p.vmod = TMod(float(vm[0]), float(vm[1]), float(vm[2]), int(vm[3]))
+    for j, m in enumerate(getattr(inst, "wmod", ((0.0, 0.0, 0.0, 0),) * 3)):
+        p.wmod[j] = TMod(float(m[0]), float(m[1]), float(m[2]), int(m[3]))
     return p
 
 

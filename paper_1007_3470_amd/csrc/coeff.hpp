@@ -300,7 +300,8 @@ __host__ __device__ inline void coupled_wmat(const InstDev &I, int d, double t, 
                 W[i * d + j] = tf_square(I.om[i], t);
             } else {
                 const int a = i < j ? i : j, b = i < j ? j : i;
-                W[i * d + j] = I.wx[a + b - 1];  // (0,1) -> 0, (0,2) -> 1, (1,2) -> 2
+                const int k = a + b - 1;  // (0,1) -> 0, (0,2) -> 1, (1,2) -> 2
+                W[i * d + j] = I.wx[k] * tf_value(I.wxm[k], t);
             }
         }
 }

@@ -164,6 +164,46 @@ TFunc to_tf(const hfgpe_tfunc &s)
     return t;
 }
 
+// A modulation m(t) as the TFunc form v0 (1 + ...) with v0 = 1.
+TFunc to_mod(const hfgpe_tmod &s)
+{
+    TFunc t;
+    t.v0 = 1.0;
+    t.amp = s.amp;
+    t.freq = s.freq;
+    t.phase = s.phase;
+    t.kind = s.kind;
+    t.pad_ = 0;
+    return t;
+}
+
+bool tmod_ok(const hfgpe_tmod &s)
+{
+    if (!std::isfinite(s.amp) || !std::isfinite(s.freq) || !std::isfinite(s.phase)) return false;
+    if (s.kind == HFGPE_TF_SIN) return true;
+    if (s.kind == HFGPE_TF_PULSE) return s.amp == 0.0 || s.freq != 0.0;
+    return false;
+}
+
+// Largest |m(t)| over all t: 1 + |amp| for the sine; for the pulse the
+// extremes of t / cosh^2(B (t - c)), sampled densely and widened by 1%.
+double tmod_absmax(const hfgpe_tmod &s)
+{
+    if (s.amp == 0.0) return 1.0;
+    if (s.kind != HFGPE_TF_PULSE) return 1.0 + std::fabs(s.amp);
+    const double B = std::fabs(s.freq), c = s.phase;
+    double hmin = 0.0, hmax = 0.0;
+    for (int k = 0; k <= 16384; ++k) {
+        double t = c + (60.0 * k / 16384.0 - 30.0) / B;
+        double ch = std::cosh(B * (t - c));
+        double h = t / (ch * ch);
+        hmin = std::min(hmin, h);
+        hmax = std::max(hmax, h);
+    }
+    const double pad = 0.01 * (hmax - hmin);
+    return std::max(std::fabs(1.0 + s.amp * (hmin - pad)), std::fabs(1.0 + s.amp * (hmax + pad)));
+}
+
 bool tf_ok(const hfgpe_tfunc &s, bool frequency)
 {
     if (!std::isfinite(s.v0) || !std::isfinite(s.amp) || !std::isfinite(s.freq) || !std::isfinite(s.phase))
@@ -230,8 +270,13 @@ bool params_coupled(const hfgpe_params &p, int nd)
 // normal frequency, and a sampled check of the factor triples.
 int validate_coupled(const hfgpe_params &p, int nd, const SchemeDev &S, double dt)
 {
-    for (int j = 0; j < 3; ++j)
+    double wabs[3];  // largest |W_xy|, |W_xz|, |W_yz| over time
+    for (int j = 0; j < 3; ++j) {
         if (!std::isfinite(p.wcross[j])) return HFGPE_E_INVALID_ARG;
+        // the exact rule needs a constant W
+        if (S.rule == HFGPE_HO_EXACT_CONST && p.wcross[j] != 0.0 && p.wmod[j].amp != 0.0) return HFGPE_E_INVALID_ARG;
+        wabs[j] = std::fabs(p.wcross[j]) * tmod_absmax(p.wmod[j]);
+    }
     if (S.rule != HFGPE_HO_EXACT_CONST && S.rule != HFGPE_HO_CF4 && S.rule != HFGPE_FSPLIT) return HFGPE_E_INVALID_ARG;
     double amax = 0.0;
     for (int i = 0; i < S.m; ++i) amax = std::max(amax, std::fabs(S.a[i]));
@@ -242,7 +287,7 @@ int validate_coupled(const hfgpe_params &p, int nd, const SchemeDev &S, double d
         if (S.rule == HFGPE_HO_EXACT_CONST && p.omega[j].amp != 0.0) return HFGPE_E_INVALID_ARG;
         double off = 0.0;
         for (int k = 0; k < nd; ++k)
-            if (k != j) off += std::fabs(p.wcross[j + k - 1]);
+            if (k != j) off += wabs[j + k - 1];
         if (!(p.omega[j].v0 > 0.0) || !(qmin - off > 0.0)) return HFGPE_E_NONPOSITIVE_FREQ;
         lmax = std::max(lmax, qmax + off);
         if (w1 - w0 > win1 - win0) { win0 = w0; win1 = w1; }
@@ -259,7 +304,9 @@ int validate_coupled(const hfgpe_params &p, int nd, const SchemeDev &S, double d
     for (int j = 0; j < 3; ++j) {
         I.om[j] = to_tf(p.omega[j]);
         I.wx[j] = p.wcross[j];
+        I.wxm[j] = to_mod(p.wmod[j]);
     }
+    I.vmod = to_mod(p.vmod);
     for (int k = 0; k < 64; ++k) {
         double t = win0 + (win1 - win0) * k / 64.0;
         for (int e = 0; e < coupled_stages(S); ++e) {
@@ -284,6 +331,9 @@ int validate_instance(const hfgpe_params &p, int nd, const SchemeDev &S, double 
     for (int j = 0; j < 3; ++j)
         if (!tf_ok(p.omega[j], true)) return HFGPE_E_INVALID_ARG;
     if (!tf_ok(p.sigma, false)) return HFGPE_E_INVALID_ARG;
+    if (!tmod_ok(p.vmod)) return HFGPE_E_INVALID_ARG;
+    for (int j = 0; j < 3; ++j)
+        if (!tmod_ok(p.wmod[j])) return HFGPE_E_INVALID_ARG;
     for (int j = 0; j < 3; ++j) {
         const hfgpe_vfactor &v = p.v[j];
         if (!std::isfinite(v.c0) || !std::isfinite(v.c2) || !std::isfinite(v.c4) || !std::isfinite(v.gs) ||
@@ -500,7 +550,8 @@ static int host_stage_records(hfgpe_plan *P, double t0, int64_t s0, int k, int64
             }
             return HFGPE_OK;
         };
-        // sigma(t) * w, and the Fourier split's harmonic phase w mu omega_j(t)^2
+        // sigma(t) * w, the Fourier split's harmonic phase w mu omega_j(t)^2, and
+        // the time factor of eps V_I on the weight w
         auto b_terms = [&](Rec &r, double t) -> int {
             const double sg = coef ? P->coef_fn(P->coef_user, inst, 3, t) : tf_value(I.sig, t);
             if (!std::isfinite(sg)) return HFGPE_E_NONFINITE;
@@ -513,6 +564,7 @@ static int host_stage_records(hfgpe_plan *P, double t0, int64_t s0, int k, int64
                     r.chi[j] += r.w * I.mu * q;
                 }
             }
+            r.w *= tf_value(I.vmod, t);
             return HFGPE_OK;
         };
         for (int s = 0; s < k; ++s) {
@@ -839,7 +891,11 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
         I.mu = p.mu;
         I.eps = p.eps;
         I.sig = to_tf(p.sigma);
-        for (int j = 0; j < 3; ++j) I.wx[j] = (nd >= 2) ? p.wcross[j] : 0.0;
+        for (int j = 0; j < 3; ++j) {
+            I.wx[j] = (nd >= 2) ? p.wcross[j] : 0.0;
+            I.wxm[j] = to_mod(p.wmod[j]);
+        }
+        I.vmod = to_mod(p.vmod);
         I.coupled = coupled ? 1 : 0;
         P->offsets[k] = off;
         off += pts;
@@ -1312,7 +1368,9 @@ int hfgpe_stage_coeffs_coupled(const hfgpe_params *params, int ndim, const hfgpe
     for (int j = 0; j < 3; ++j) {
         I.om[j] = to_tf(params->omega[j]);
         I.wx[j] = params->wcross[j];
+        I.wxm[j] = to_mod(params->wmod[j]);
     }
+    I.vmod = to_mod(params->vmod);
     const int me = coupled_stages(S), dd = ndim * ndim;
     for (int k = 0; k < me; ++k) {
         double F[9], G[9];

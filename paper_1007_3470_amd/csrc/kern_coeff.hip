@@ -66,6 +66,7 @@ __global__ __launch_bounds__(128) void coeff_kernel(const InstDev *__restrict__ 
 #pragma unroll
             for (int j = 0; j < ND; ++j) o.chi[j] += o.w * mu * tf_square(I.om[j], tn);
         }
+        o.w *= tf_value(I.vmod, tn);  // eps V_I(x, t) = m(t) eps V_I(x)
         rec_open[inst] = o;
     }
     for (int i = 0; i < m; ++i) {
@@ -108,6 +109,7 @@ __global__ __launch_bounds__(128) void coeff_kernel(const InstDev *__restrict__ 
 #pragma unroll
             for (int j = 0; j < ND; ++j) r.chi[j] += r.w * mu * tf_square(I.om[j], tau_next);
         }
+        r.w *= tf_value(I.vmod, tau_next);
         bool finite = isfinite(r.w) && isfinite(r.s);
 #pragma unroll
         for (int j = 0; j < 3; ++j) finite = finite && isfinite(r.g[j]) && isfinite(r.chi[j]);
@@ -175,6 +177,7 @@ __global__ void coeff_coupled_kernel(const InstDev *__restrict__ insts, int n_in
         o.w = dt * S.b[0];
         add_harm(C, o.w, tn);
         o.s = o.w * tf_value(I.sig, tn);
+        o.w *= tf_value(I.vmod, tn);
         store_mats(d, Z, C, o, ox);
         rec_open[inst] = o;
         recx_open[inst] = ox;
@@ -206,7 +209,7 @@ __global__ void coeff_coupled_kernel(const InstDev *__restrict__ insts, int n_in
             tau_next = tn1;
         }
         if (!half) add_harm(C, w, tau_next);
-        r.w = w;
+        r.w = half ? 0.0 : w * tf_value(I.vmod, tau_next);
         r.s = half ? 0.0 : w * tf_value(I.sig, tau_next);
         store_mats(d, G, C, r, x);
         bool finite = isfinite(r.w) && isfinite(r.s);

@@ -43,7 +43,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(const InstDev *__restrict__
     for (int j = 0; j < 3; ++j) {
         hw[j] = (j < nd) ? 0.5 * I.mu * tf_square(I.om[j], t) : 0.0;
     }
-    const double sig = tf_value(I.sig, t);
+    const double sig = tf_value(I.sig, t), vm = tf_value(I.vmod, t);
+    double wx[3];  // W_xy, W_xz, W_yz at t
+    for (int k = 0; k < 3; ++k) wx[k] = I.wx[k] * tf_value(I.wxm[k], t);
     Ksum a, b, c;
     for (int64_t idx = (int64_t)blk * 256 + threadIdx.x; idx < total; idx += (int64_t)nblk * 256) {
         double re = (double)u[idx].x, im = (double)u[idx].y;
@@ -61,8 +63,8 @@ __global__ __launch_bounds__(256) void reduce_kernel(const InstDev *__restrict__
                 VI *= vfactor(I.vf[j], x);
             }
             if (I.coupled)  // off-diagonal part of (mu/2) x^T W x
-                V += I.mu * (I.wx[0] * xs[0] * xs[1] + I.wx[1] * xs[0] * xs[2] + I.wx[2] * xs[1] * xs[2]);
-            V += vi ? vi[I.offset + idx] : I.eps * VI;
+                V += I.mu * (wx[0] * xs[0] * xs[1] + wx[1] * xs[0] * xs[2] + wx[2] * xs[1] * xs[2]);
+            V += vm * (vi ? vi[I.offset + idx] : I.eps * VI);
             b.add(V * a2);
             c.add(0.5 * sig * a2 * a2);
         }

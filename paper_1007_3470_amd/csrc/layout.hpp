@@ -37,9 +37,11 @@ struct InstDev {
     TFunc om[3];
     TFunc sig;
     VFac vf[3];
-    double wx[3];  // coupled trap: constant W_xy, W_xz, W_yz of (mu/2) x^T W x
+    double wx[3];  // coupled trap: W_xy, W_xz, W_yz of (mu/2) x^T W x, times wxm
     int coupled;   // 1 when some wx used by the grid's axes is non-zero
     int pad2_;
+    TFunc vmod;    // time factor of eps V_I (v0 = 1; amp = 0: constant 1)
+    TFunc wxm[3];  // time factors of W_xy, W_xz, W_yz (v0 = 1)
 };
 
 // The pointwise x-space phase applied after stage i of a step:

@@ -51,7 +51,7 @@ def test_version_and_status_strings():
     lib = pkg.load()
     ma, mi = ctypes.c_int(), ctypes.c_int()
     assert lib.hfgpe_version(ctypes.byref(ma), ctypes.byref(mi)) == 0
-    assert (ma.value, mi.value) == (0, 1)
+    assert (ma.value, mi.value) == (0, 2)
     for code in range(-8, 1):
         assert lib.hfgpe_status_string(code).decode() != "unknown status"
     assert lib.hfgpe_status_string(-99).decode() == "unknown status"
@@ -286,3 +286,38 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", w.dt)
     with pytest.raises(ImportError):
         pkg.scheme_preset("leapfrog")
+
+
+# modulated cross terms W_ij(t) and a time factor of eps V_I
+WMOD = ((0.5, 2.3, 0.4, 0), (0.8, 2.0, 0.6, 2), (-0.4, 1.1, 0.0, 0))
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("scheme,dt", [("leapfrog", 0.05), ("ni5_84", -0.1), ("srkn6_4", 0.2)])
+def test_modulated_coupled_triples_match_oracle(d, scheme, dt):
+    for mu, tn in ((1.0, 0.0), (1.7, 1.3)):
+        inst = replace(_coupled_inst(d, mu=mu), wmod=WMOD)
+        lib_t = pkg.stage_coeffs_coupled(inst, scheme, "cf4", dt, tn)
+        orc_t = oracle.stage_coeffs_full(inst, scheme, "cf4", dt, tn)
+        scale = np.abs(orc_t).max()
+        assert np.abs(lib_t - orc_t).max() < 1e-13 * scale, np.abs(lib_t - orc_t).max()
+        # and the modulation is not a no-op
+        plain = pkg.stage_coeffs_coupled(_coupled_inst(d, mu=mu), scheme, "cf4", dt, tn)
+        assert np.abs(plain - lib_t).max() > 1e-6 * scale
+
+
+def test_modulation_validation():
+    base = W.gpe_2d(n=16, n_inst=1, nsteps=0).instances[0]
+    cpl = replace(base, wcross=(0.2, 0.0, 0.0), wmod=((0.5, 1.0, 0.0, 0),) + ((0.0, 0.0, 0.0, 0),) * 2)
+    assert _gpu_or_nodevice(_create([cpl], rule="cf4"))
+    assert _gpu_or_nodevice(_create([cpl], rule="fsplit"))
+    const = replace(cpl, omega=((1.0, 0.0, 0.0, 0.0), (1.5, 0.0, 0.0, 0.0), W.CONST_OMEGA))
+    assert _create([const], rule="exact_const", dt=1.0) == -1          # W(t) not constant
+    unmod = replace(const, wmod=((0.0, 0.0, 0.0, 0),) * 3)
+    assert _gpu_or_nodevice(_create([unmod], rule="exact_const", dt=1.0))
+    # |W_xy| reaches 0.2 * 1.5 = 0.3; with wcross 0.6 it reaches 0.9 > omega_x^2 - ... (indefinite)
+    assert _create([replace(cpl, wcross=(1.2, 0.0, 0.0))], rule="cf4") == -4
+    assert _create([replace(cpl, wmod=((0.5, 1.0, 0.0, 1),) + cpl.wmod[1:])], rule="cf4") == -1   # no kind 1
+    assert _create([replace(cpl, wmod=((0.5, 0.0, 0.0, 2),) + cpl.wmod[1:])], rule="cf4") == -1   # pulse freq 0
+    assert _create([replace(base, vmod=(float("inf"), 1.0, 0.0, 0))]) == -1
+    assert _gpu_or_nodevice(_create([replace(base, vmod=(0.5, 1.0, 0.0, 2))]))

@@ -262,7 +262,8 @@ def test_batch_1d_full_size_sampled(pkg, dtype):
     n0 = np.array([oracle.norm(i, p) for i, p in zip(w.instances, w.psi0)])
     drift = np.abs(nrm - n0).max()
     say("batch_1d full %s max norm drift %.3e" % (dtype, drift))
-    assert drift < (1e-11 if dtype == "c128" else 1e-4)
+    # measured: c128 under 1e-12, c64 5e-8 (the state is stored in c64 once per launch)
+    assert drift < (1e-11 if dtype == "c128" else 5e-7)
 
 
 @pytest.mark.parametrize("scheme", ["leapfrog", "ni4_82", "srkn6_4"])
@@ -340,7 +341,7 @@ def test_c64_error_grows_like_sqrt_n(pkg):
     drift = abs(plans["c128"].norm(bufs["c128"])[0] / n0 - 1.0)
     say("c64 vs c128 at 1e2/1e3/1e4 steps: %s (growth exponent %.2f); c128 norm drift %.1e"
         % (", ".join("%.2e" % e for e in errs), slope, drift))
-    assert slope < 0.9 and errs[2] < 5e-5
+    assert slope < 0.8 and errs[2] < 5e-5
     assert drift < 1e-12
 
 

@@ -1,5 +1,6 @@
-"""Pins of the oracle's coupled trap: V_HO = (mu/2) x^T W(t) x with constant
-off-diagonal entries (the general quadratic potential x^T M x of Sec. 1).
+"""Pins of the oracle's coupled trap: V_HO = (mu/2) x^T W(t) x with
+off-diagonal entries, constant or modulated in time (the general quadratic
+potential x^T M(t) x of Sec. 1).
 
 Expected values come from outside the oracle: scipy's matrix exponential and
 DOP853 integrations of the 2d x 2d classical system, the d-dimensional
@@ -16,8 +17,17 @@ import oracle
 import workloads as W
 
 
+def modulation(m, t):
+    """m(t) of a (amp, freq, phase, form) modulation, from its definition."""
+    amp, fr, ph, form = m
+    if form == 2:
+        return 1.0 + amp * t / math.cosh(fr * (t - ph)) ** 2
+    return 1.0 + amp * math.sin(fr * t + ph)
+
+
 def wmat(inst, t):
-    """W(t) written from its definition: W_jj = omega_j(t)^2, W_ij = wcross."""
+    """W(t) written from its definition: W_jj = omega_j(t)^2, W_ij = wcross
+    times its modulation."""
     d = inst.ndim
     M = np.zeros((d, d))
     for j in range(d):
@@ -26,7 +36,7 @@ def wmat(inst, t):
     pairs = {(0, 1): 0, (0, 2): 1, (1, 2): 2}
     for (i, j), k in pairs.items():
         if i < d and j < d:
-            M[i, j] = M[j, i] = inst.wcross[k]
+            M[i, j] = M[j, i] = inst.wcross[k] * modulation(inst.wmod[k], t)
     return M
 
 
@@ -42,13 +52,18 @@ def flow_dop853(inst, t0, tau):
     return sol.y[:, -1].reshape(n, n)
 
 
-def coupled(d=2, n=32, mu=1.0, omega=None, wcross=(0.3, 0.2, -0.25), L=6.0):
+NO_MOD = ((0.0, 0.0, 0.0, 0),) * 3
+# modulated cross terms: a sine on W_xy, a pulse on W_xz, a sine on W_yz
+WMOD = ((0.5, 2.3, 0.4, 0), (0.8, 2.0, 0.6, 2), (-0.4, 1.1, 0.0, 0))
+
+
+def coupled(d=2, n=32, mu=1.0, omega=None, wcross=(0.3, 0.2, -0.25), L=6.0, wmod=NO_MOD):
     if omega is None:
         omega = ((1.2, 0.2, 1.5, 0.3), (0.9, 0.0, 0.0, 0.0), (1.4, 0.1, 0.7, 0.0))
     nn = tuple([n] * d + [1] * (3 - d))
     lo = tuple([-L] * d + [0.0] * (3 - d))
     hi = tuple([L] * d + [1.0] * (3 - d))
-    return W.Instance(d, nn, lo, hi, mu=mu, omega=tuple(omega[:3]), wcross=tuple(wcross))
+    return W.Instance(d, nn, lo, hi, mu=mu, omega=tuple(omega[:3]), wcross=tuple(wcross), wmod=tuple(wmod))
 
 
 CONST = ((1.2, 0.0, 0.0, 0.0), (0.9, 0.0, 0.0, 0.0), (1.4, 0.0, 0.0, 0.0))
@@ -217,3 +232,64 @@ def test_coupled_potential_energy():
     t = 0.7
     e = oracle.energy(inst, u, t)
     assert abs(e[2] - 0.5 * inst.mu * np.trace(wmat(inst, t) @ Sigma)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# modulated cross terms W_ij(t) (Sec. 1's M(t))
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d", [2, 3])
+def test_cf4_local_order_modulated_cross_terms(d):
+    """The commutator-free rule averages the whole W(t), cross terms included,
+    at its Gauss nodes: local order 4 against DOP853 of the classical system."""
+    inst = coupled(d=d, mu=1.3, wmod=WMOD)
+    errs = []
+    for tau in (0.2, 0.1, 0.05):
+        S = oracle.stage_matrix_full(inst, "cf4", 0.4, tau)
+        errs.append(np.abs(S - flow_dop853(inst, 0.4, tau)).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 4.6, (errs, rates)
+    # a rule that froze the cross terms at the stage start would lose the order:
+    # the same instance with W_ij held at their t = 0.4 values differs at O(tau^2)
+    frozen = coupled(d=d, mu=1.3, wmod=NO_MOD,
+                     wcross=tuple(c * modulation(m, 0.4) for c, m in zip((0.3, 0.2, -0.25), WMOD)))
+    e_frozen = np.abs(oracle.stage_matrix_full(frozen, "cf4", 0.4, 0.05) - flow_dop853(inst, 0.4, 0.05)).max()
+    assert e_frozen > 100 * errs[-1]
+
+
+@pytest.mark.parametrize("scheme,rule,order", [("leapfrog", "cf4", 4), ("ni5_84", "cf4", 4),
+                                               ("leapfrog", "fsplit", 2), ("ni5_84", "fsplit", 4)])
+def test_modulated_coupled_order(scheme, rule, order):
+    """Linear evolution with W_xy(t) modulated: global order against the
+    Gaussian packet of the matrix Riccati equation."""
+    inst = coupled(d=2, n=128, mu=1.0, L=12.0, wcross=(0.35, 0.0, 0.0), wmod=WMOD)
+    A0, b0, psi0 = initial_packet(inst, (0.5, -0.3, 0.0))
+    T = 1.0
+    ref = gaussian_packet(inst, A0, b0, 0j, 0.0, T)
+    errs = []
+    for nst in (8, 16, 32):
+        errs.append(W.rel_l2(oracle.evolve(inst, psi0, scheme, rule, T / nst, 0.0, nst), ref))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > order - 0.4, (errs, rates)
+
+
+def test_modulated_coupled_3d_order():
+    inst = coupled(d=3, n=64, mu=1.1, L=10.0, wmod=WMOD)
+    A0, b0, psi0 = initial_packet(inst, (0.4, -0.3, 0.2))
+    T = 0.8
+    ref = gaussian_packet(inst, A0, b0, 0j, 0.0, T)
+    errs = [W.rel_l2(oracle.evolve(inst, psi0, "leapfrog", "cf4", T / n, 0.0, n, threads=4), ref)
+            for n in (8, 16, 32)]
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(rates) > 3.6, (errs, rates)
+
+
+def test_modulated_coupled_potential_energy():
+    inst = coupled(d=2, n=128, mu=1.4, wcross=(0.4, 0.0, 0.0), L=9.0, wmod=WMOD)
+    P = np.array([[1.0, 0.3], [0.3, 0.8]])
+    X = np.stack([m * np.ones(inst.shape) for m in inst.mesh()], axis=-1)
+    u = np.exp(-0.5 * np.einsum("...i,ij,...j->...", X, P, X)).astype(complex)
+    u /= math.sqrt(inst.cell * np.sum(np.abs(u) ** 2))
+    Sigma = np.linalg.inv(2.0 * P)
+    for t in (0.0, 0.7, 2.1):
+        e = oracle.energy(inst, u, t)
+        assert abs(e[2] - 0.5 * inst.mu * np.trace(wmat(inst, t) @ Sigma)) < 1e-12

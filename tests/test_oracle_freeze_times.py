@@ -216,3 +216,53 @@ def test_observed_order_with_sigma_t(sig):
     assert min(r) > 3.6, r
     r = _rates(errs("leapfrog", (20, 40, 80), frozen=True))
     assert max(r) < 1.3, r
+
+
+# ---------------------------------------------------------------------------
+# a time factor of eps V_I: on the one-point grid the phase gains
+# eps V_I h sum_i b_i m(tau_i)
+# ---------------------------------------------------------------------------
+VMODS = [(0.7, 2.5, 0.3, 0), (0.9, 2.0, 0.8, 2)]
+
+
+def vmod_of(vm, t):
+    amp, fr, ph, form = vm
+    if form == 2:
+        return 1.0 + amp * t / math.cosh(fr * (t - ph)) ** 2
+    return 1.0 + amp * math.sin(fr * t + ph)
+
+
+@pytest.mark.parametrize("scheme", ["leapfrog", "ni5_84"])
+@pytest.mark.parametrize("vm", VMODS)
+def test_point_grid_vi_time_factor(scheme, vm):
+    inst = replace(point_instance(SIG_SINE), vmod=vm)
+    a, b = _golden_scheme(scheme)
+    c = np.concatenate([[0.0], np.cumsum(a)])
+    t0, h, n = 0.3, 0.05, 24
+    u = oracle.evolve(inst, U0, scheme, "cf4", h, t0, n)
+    expect = sum(h * b[i] * (0.3 * 2.0 * vmod_of(vm, t0 + s * h + h * c[i])
+                             + sigma_of(SIG_SINE, t0 + s * h + h * c[i]) * abs(U0[0]) ** 2)
+                 for s in range(n) for i in range(len(b)))
+    assert abs(wrap(point_phase(u) - expect)) < 1e-12
+
+
+def test_point_grid_vi_time_factor_order():
+    """Against the closed-form integral of the sine factor: order 2 for
+    leapfrog, order 1 for the factor held at t_n."""
+    vm = VMODS[0]
+    amp, fr, ph, _ = vm
+    t0, T = 0.3, 1.0
+    inst = replace(point_instance((0.0, 0.0, 0.0, 0.0, 0)), vmod=vm)     # sigma = 0
+    exact = 0.3 * 2.0 * (T - amp / fr * (math.cos(fr * (t0 + T) + ph) - math.cos(fr * t0 + ph)))
+    errs, wrong = [], []
+    for n in (10, 20, 40, 80):
+        h = T / n
+        errs.append(abs(wrap(point_phase(oracle.evolve(inst, U0, "leapfrog", "cf4", h, t0, n)) - exact)))
+        u = U0.copy()
+        for s in range(n):
+            tn = t0 + s * h
+            held = replace(point_instance((0.0, 0.0, 0.0, 0.0, 0), eps=0.3 * vmod_of(vm, tn)), vmod=(0.0, 0.0, 0.0, 0))
+            u = oracle.evolve(held, u, "leapfrog", "cf4", h, tn, 1)
+        wrong.append(abs(wrap(point_phase(u) - exact)))
+    assert min(_rates(errs)) > 1.9, errs
+    assert max(_rates(wrong)) < 1.2, wrong

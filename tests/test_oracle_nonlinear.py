@@ -15,6 +15,9 @@ oracle's output, not with the oracle's own FFT or energy routine.
   sigma = 30, steps of 0.05 let high wavenumbers grow and it fails at 1e-2).
   With the commutator-free rule it carries exactly that rule's classical error
   (global order 4).
+* Forced Kohn mode: with a uniform, time-dependent force (eps V_I(x, t) =
+  m(t) F x) the centre of mass is the classical split map with the B kicks
+  at the stage times, for any sigma.
 * 2-D breathing mode: in a 2-D isotropic trap the virial identity gives
   <r^2>'' = 4 E / mu - 4 omega^2 <r^2> exactly for the cubic nonlinearity, E the
   conserved energy including (sigma/2) int rho^2; a wrong weight or sign of the
@@ -170,3 +173,83 @@ def test_breathing_mode_2d(sigma):
     wrong = W.Instance(**{**inst.__dict__, "sigma": (0.5 * sigma, 0.0, 0.0, 0.0)})
     u = oracle.evolve(wrong, u0, "ni5_84", "exact_const", T / 60, 0.0, 60)
     assert abs(float((r2 * np.abs(u) ** 2).sum()) * h - exact) > 1e3 * errs[1]
+
+
+# ---------------------------------------------------------------------------
+# time-dependent perturbation eps V_I(x, t) = m(t) F x (Sec. 1): a uniform,
+# time-dependent force.  For any sigma the centre of mass obeys
+# x' = p/mu, p' = -mu omega^2 x - F m(t); the HO split moves (<x>, <p>) by the
+# stage's classical matrix in A (exact rule: Lemma 2) and kicks <p> by
+# -h b_i F m(tau_i) in each B flow, the mean field giving no net force.  So the
+# oracle's centre of mass must equal that classical split map applied to
+# (x0, p0) with the B kicks at the stage times of Table "algorithm", and
+# converge to the forced orbit (DOP853) at the scheme's order.
+# ---------------------------------------------------------------------------
+def _forced_setup(vmod, sigma=20.0):
+    mu, w, F = 1.3, 1.1, 0.3
+    inst = W.Instance(1, (512, 1, 1), (-16.0, 0.0, 0.0), (16.0, 1.0, 1.0), mu=mu,
+                      omega=((w, 0.0, 0.0, 0.0), CONST, CONST), sigma=(sigma, 0.0, 0.0, 0.0), eps=1.0,
+                      vmod=vmod)
+    x = inst.axis(0)
+    return inst, mu, w, F, F * x
+
+
+def _m(vmod, t):
+    amp, fr, ph, form = vmod
+    if form == 2:
+        return 1.0 + amp * t / math.cosh(fr * (t - ph)) ** 2
+    return 1.0 + amp * math.sin(fr * t + ph)
+
+
+def _classical_split(scheme, mu, w, F, vmod, x0, p0, t0, h, n):
+    a, b = oracle.scheme_coefficients(scheme)
+    z = np.array([x0, p0])
+    for s in range(n):
+        tau = t0 + s * h
+        z[1] -= h * b[0] * F * _m(vmod, tau)
+        for i in range(len(a)):
+            th = w * a[i] * h
+            R = np.array([[math.cos(th), math.sin(th) / (mu * w)], [-mu * w * math.sin(th), math.cos(th)]])
+            z = R @ z
+            tau = tau + a[i] * h
+            z[1] -= h * b[i + 1] * F * _m(vmod, tau)
+    return z
+
+
+@pytest.mark.parametrize("vmod", [(0.6, 2.0, 0.3, 0), (0.9, 1.5, 1.0, 2)])
+@pytest.mark.parametrize("scheme", ["leapfrog", "ni5_84"])
+def test_forced_kohn_mode_is_the_classical_split(vmod, scheme):
+    inst, mu, w, F, vi = _forced_setup(vmod)
+    x0, p0 = 1.2, -0.4
+    u0 = gaussian(inst, (x0,), (mu * w,), (p0,))
+    t0, h, n = 0.2, 0.02, 150
+    u = oracle.evolve(inst, u0, scheme, "exact_const", h, t0, n, vi=vi)
+    X, P = moments(inst, u)
+    z = _classical_split(scheme, mu, w, F, vmod, x0, p0, t0, h, n)
+    assert abs(X[0] - z[0]) < 1e-10 and abs(P[0] - z[1]) < 1e-10, (X, P, z)
+    # the slip of holding m at t_n over the whole step misses by far more
+    wrong = np.array([x0, p0])
+    for s in range(n):
+        tn = t0 + s * h
+        frozen = (0.0, 0.0, 0.0, 0)
+        wrong = _classical_split(scheme, mu, w, F * _m(vmod, tn), frozen, wrong[0], wrong[1], tn, h, 1)
+    assert abs(wrong[0] - z[0]) + abs(wrong[1] - z[1]) > 1e-5
+
+
+def test_forced_kohn_mode_order():
+    """The centre of mass converges to the forced orbit (DOP853) at order 2
+    (leapfrog) and 4 (NI5), with sigma = 20 acting on the density."""
+    vmod = (0.6, 2.0, 0.3, 0)
+    inst, mu, w, F, vi = _forced_setup(vmod)
+    x0, p0, t0, T = 1.2, -0.4, 0.2, 2.0
+    u0 = gaussian(inst, (x0,), (mu * w,), (p0,))
+    sol = solve_ivp(lambda t, y: [y[1] / mu, -mu * w * w * y[0] - F * _m(vmod, t)], (t0, t0 + T), [x0, p0],
+                    method="DOP853", rtol=1e-13, atol=1e-14)
+    ref = sol.y[:, -1]
+    for scheme, steps, order in (("leapfrog", (40, 80, 160), 2), ("ni5_84", (20, 40, 80), 4)):
+        errs = []
+        for n in steps:
+            X, P = moments(inst, oracle.evolve(inst, u0, scheme, "exact_const", T / n, t0, n, vi=vi))
+            errs.append(abs(X[0] - ref[0]) + abs(P[0] - ref[1]))
+        rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+        assert min(rates) > order - 0.3, (scheme, errs, rates)

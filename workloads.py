@@ -47,9 +47,15 @@ class Instance:
     sigma: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
     eps: float = 0.0
     vfac: Tuple[Tuple[float, ...], ...] = (NO_V,) * 3
-    # constant off-diagonal W_xy, W_xz, W_yz of the squared-frequency matrix of a
-    # coupled trap V_HO = (mu/2) x^T W(t) x, W_jj = omega_j(t)^2
+    # off-diagonal W_xy, W_xz, W_yz of the squared-frequency matrix of a coupled
+    # trap V_HO = (mu/2) x^T W(t) x, W_jj = omega_j(t)^2, each times its
+    # modulation in wmod
     wcross: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    # time modulations (amp, freq, phase, form) of eps V_I and of W_xy, W_xz,
+    # W_yz: form 0: m(t) = 1 + amp sin(freq t + phase); form 2: m(t) = 1 + amp t
+    # / cosh^2(freq (t - phase)); all zero: static
+    vmod: Tuple[float, float, float, int] = (0.0, 0.0, 0.0, 0)
+    wmod: Tuple[Tuple[float, float, float, int], ...] = ((0.0, 0.0, 0.0, 0),) * 3
 
     @property
     def points(self) -> int:
