@@ -59,6 +59,8 @@ extern "C" {
 #define HFGPE_E_HIP (-6)               /* a HIP call failed; hfgpe_last_hip_error */
 #define HFGPE_E_NONFINITE (-7)         /* a coefficient came out NaN/Inf        */
 #define HFGPE_E_NO_DEVICE (-8)         /* no usable gfx950 device               */
+#define HFGPE_E_SCRATCH (-9)           /* the request exceeds the static scratch of an
+                                          allocation-free entry point           */
 
 /* Largest grid extent per axis supported by the resident kernels. */
 #define HFGPE_MAX_N_1D 4096
@@ -277,8 +279,31 @@ int hfgpe_set_coef_callback(hfgpe_plan *plan, hfgpe_coef_fn fn, void *user);
 int hfgpe_set_potential(hfgpe_plan *plan, const double *d_vi);
 
 /* Discrete squared norm h^d sum |u|^2 of every instance into the host array
- * h_out[n_inst] (FP64, compensated summation).  Synchronises the stream. */
+ * h_out[n_inst] (FP64, compensated summation): the norm that the GPE and its
+ * split flows preserve (Sec. 1; Lemma 1 for the B flow).  Synchronises the
+ * stream. */
 int hfgpe_norm(hfgpe_plan *plan, const void *d_psi, double *h_out);
+
+/* Bytes of the static device scratch of hfgpe_norm_noalloc. */
+#define HFGPE_NOALLOC_SCRATCH_BYTES (1u << 20)
+
+/* Allocation-free variant of hfgpe_norm, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same compensated sums, with the per-block partial sums
+ * kept in a file-scope static device array of HFGPE_NOALLOC_SCRATCH_BYTES
+ * (one per GPU, held until the process ends) instead of the plan's
+ * workspace, and the per-instance results written to the caller's device
+ * array d_out[n_inst] (FP64, 8-byte aligned).  Stream-ordered on the plan's
+ * stream and asynchronous: nothing is allocated, copied to the host or
+ * synchronised.  The plan is used on the device it was created on.
+ * Requires n_inst * (partial blocks per instance) * 32 bytes of scratch:
+ * HFGPE_E_SCRATCH when that exceeds HFGPE_NOALLOC_SCRATCH_BYTES (nothing is
+ * launched).  Every call on a GPU shares that GPU's array, so calls that
+ * overlap in time on one GPU (other streams, other threads) race; the array
+ * needs no clearing (each call writes every partial it reads).
+ * INVALID_ARG for a NULL plan, d_psi or d_out (n_inst > 0) or misaligned
+ * buffers. */
+int hfgpe_norm_noalloc(hfgpe_plan *plan, const void *d_psi, double *d_out);
 
 /* GPE energy of every instance at time t into h_out[4*n_inst]:
  * (total, kinetic, potential, interaction) per instance, with

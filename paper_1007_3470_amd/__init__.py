@@ -27,7 +27,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "si
           -4: "non-positive frequency", -5: "allocation failed", -6: "HIP error",
           -7: "non-finite coefficient", -8: "no gfx950 device"}
 SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", "hfgpe_evolve",
-           "hfgpe_norm", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
+           "hfgpe_norm", "hfgpe_norm_noalloc", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
            "hfgpe_stage_coeffs_coupled", "hfgpe_set_potential", "hfgpe_set_stage_callback",
            "hfgpe_set_coef_callback",
            "hfgpe_scheme_preset",
@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
     lib.hfgpe_instance_offsets.argtypes = [vp, i64p]
     lib.hfgpe_evolve.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int64]
     lib.hfgpe_norm.argtypes = [vp, vp, dp]
+    lib.hfgpe_norm_noalloc.argtypes = [vp, vp, vp]
     lib.hfgpe_set_potential.argtypes = [vp, vp]
     lib.hfgpe_set_stage_callback.argtypes = [vp, STAGE_FN, vp]
     lib.hfgpe_set_coef_callback.argtypes = [vp, COEF_FN, vp]

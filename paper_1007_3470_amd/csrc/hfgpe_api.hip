@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -115,6 +116,7 @@ struct hfgpe_plan {
     int kin_nblk = 1;
     int nd_grid = 0;  // d-D persistent workgroups per pass; 0: per kernel instance
     int n_cu = 1;     // compute units of the plan's device
+    int device = 0;   // the HIP device the plan was created on
     // profiling: (start, stop) event pairs recorded on the plan's stream
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_coeff, ev_pool;
 
@@ -741,6 +743,59 @@ static int nd_graph_ready(hfgpe_plan *P, void *d_psi, int rec_steps)
     return HFGPE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free norm.  The per-block partial sums of the norm reduction go
+// to a file-scope static device array instead of the plan's workspace; its
+// device address is looked up once per device (hipGetSymbolAddress, with
+// that device current) and only that address is handed to kernels and copies
+// -- in host code the array's name is a host-side stand-in, not a device
+// address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[HFGPE_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kNoAllocDevices] = {};
+
+// Device address of `scratch` on device dev (which must be current).
+int scratch_address(int dev, double **out)
+{
+    if (dev < 0 || dev >= kNoAllocDevices) return HFGPE_E_NO_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_last_hip_error = (int)e;
+            return HFGPE_E_HIP;
+        }
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return HFGPE_OK;
+}
+}  // namespace
+
+// out[k] = cell_k * (compensated sum of the nblk partials of instance k), the
+// partials taken in index order as hfgpe_norm adds them on the host.
+__global__ void norm_combine_kernel(const InstDev *__restrict__ insts, int n_inst, int nblk,
+                                    const double *__restrict__ part, double *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    const InstDev &I = insts[k];
+    double s = 0.0, c = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        const double x = part[((size_t)k * nblk + b) * 4];
+        const double t = s + x;
+        c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+    const double cell = I.dx[0] * (I.ndim > 1 ? I.dx[1] : 1.0) * (I.ndim > 2 ? I.dx[2] : 1.0);
+    out[k] = cell * (s + c);
+}
+
 extern "C" {
 
 const char *hfgpe_status_string(int status)
@@ -755,6 +810,7 @@ const char *hfgpe_status_string(int status)
     case HFGPE_E_HIP: return "HIP runtime error";
     case HFGPE_E_NONFINITE: return "non-finite coefficient";
     case HFGPE_E_NO_DEVICE: return "no gfx950 device";
+    case HFGPE_E_SCRATCH: return "request exceeds the static scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }
@@ -850,6 +906,10 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
 
     hfgpe_plan *P = new (std::nothrow) hfgpe_plan();
     if (!P) return HFGPE_E_ALLOC;
+    if (n_inst > 0 && hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return HFGPE_E_HIP;
+    }
     P->n_inst = n_inst;
     P->ndim = nd;
     P->dtype = dtype;
@@ -1518,6 +1578,53 @@ int hfgpe_profile(hfgpe_plan *P, double *step_ms, double *coeff_ms, int64_t *ste
         v->clear();
     }
     return HFGPE_OK;
+}
+
+int hfgpe_norm_noalloc(hfgpe_plan *P, const void *d_psi, double *d_out)
+{
+    if (!P) return HFGPE_E_INVALID_ARG;
+    if (P->n_inst == 0) return HFGPE_OK;
+    if (!d_psi || !state_aligned(P, d_psi) || !d_out || reinterpret_cast<uintptr_t>(d_out) % 8u != 0)
+        return HFGPE_E_INVALID_ARG;
+    const size_t need = sizeof(double) * 4 * (size_t)P->n_inst * (size_t)P->nblk;
+    if (need > HFGPE_NOALLOC_SCRATCH_BYTES) return HFGPE_E_SCRATCH;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != P->device) HIP_TRY(hipSetDevice(P->device));
+    double *part = nullptr;
+    int rc = scratch_address(P->device, &part);
+    hipError_t e = hipSuccess;
+    if (rc == HFGPE_OK) {
+        LaunchReduce R;
+        R.insts = P->d_insts;
+        R.n_inst = P->n_inst;
+        R.nblk = P->nblk;
+        R.psi = d_psi;
+        R.c64 = P->dtype == HFGPE_C64;
+        R.energy = 0;
+        R.t = 0.0;
+        R.vi = nullptr;
+        R.part = part;
+        R.stream = P->stream;
+        e = launch_reduce_pointwise(R);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(norm_combine_kernel, dim3((P->n_inst + 127) / 128), dim3(128), 0, P->stream,
+                               P->d_insts, P->n_inst, P->nblk, (const double *)part, d_out);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) {
+            g_last_hip_error = (int)e;
+            rc = HFGPE_E_HIP;
+        }
+    }
+    if (cur != P->device) {
+        hipError_t er = hipSetDevice(cur);
+        if (er != hipSuccess && rc == HFGPE_OK) {
+            g_last_hip_error = (int)er;
+            rc = HFGPE_E_HIP;
+        }
+    }
+    return rc;
 }
 
 int hfgpe_device_status(hfgpe_plan *P)
