@@ -101,7 +101,7 @@ def nd_passes_per_step(pkg, w) -> int:
     return (2 * m if w.ho_rule == "cf4" else m) * (2 * d - 1)
 
 
-def nd_workload(pkg, torch, W, w, reps=5):
+def nd_workload(pkg, torch, W, w, reps=5, tune=True):
     """Secondary measurement: a d-D workload at full size and length, c64 and
     c128, steps replayed from hipGraph blocks.  The run is timed with HIP
     events on the plan's stream, median of `reps` runs from the same input;
@@ -112,6 +112,9 @@ def nd_workload(pkg, torch, W, w, reps=5):
     npass = nd_passes_per_step(pkg, w)
     for dtype, sc in (("c64", 8), ("c128", 16)):
         plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, use_graph=True)
+        # per-pass tuning on a scratch copy of the input (bitwise the same results)
+        if tune:
+            plan.autotune(w.psi0, trial_steps=8)
         scratch = plan.pack(w.psi0)
         plan.evolve(scratch, 0.0, 2)
         del scratch
@@ -132,6 +135,7 @@ def nd_workload(pkg, torch, W, w, reps=5):
         bw = 2.0 * sc * w.points / pass_s / 1e9
         out[dtype] = {"value": w.points * w.nsteps / run_s, "ms_per_step": run_s * 1e3 / w.nsteps,
                       "runs_s": [round(r, 6) for r in runs], "passes_per_step": npass,
+                      "tuned_passes": [list(t) for t in plan.tune_settings()],
                       "pass_us": pass_s * 1e6, "pass_GBs": bw, "pass_frac_of_hbm_peak": bw / HBM_PEAK_GBS}
         del plan, buf
     out["c64_pass_time_over_c128"] = out["c64"]["pass_us"] / out["c128"]["pass_us"]
@@ -350,6 +354,8 @@ def main(argv=None):
                     help="steps of the 2-D and 3-D workloads (0 = their full runs)")
     ap.add_argument("--nd-only", action="store_true",
                     help="only the 2-D and 3-D workloads (for profiling their kernels)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the d-D workloads with the default pass settings (no autotuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (HBM counter calibration)")
     ap.add_argument("--study", choices=("sec41", "sec42", "all", "precision", "mall"),
@@ -381,7 +387,7 @@ def main(argv=None):
     nd_sets = (("gpe_2d", W.gpe_2d), ("gpe_3d", W.gpe_3d), ("coupled_2d", W.coupled_2d),
                ("coupled_3d", W.coupled_3d))
     if args.nd_only:
-        print(json.dumps({"other_workloads": {name: nd_workload(pkg, torch, W, gen(**nd_kw))
+        print(json.dumps({"other_workloads": {name: nd_workload(pkg, torch, W, gen(**nd_kw), tune=not args.no_tune)
                                               for name, gen in nd_sets}}), flush=True)
         return 0
     w = W.batch_1d(nsteps=K)
@@ -438,7 +444,7 @@ def main(argv=None):
         "wall_s": {"c64": wall64, "c128": wall128},
     }
     if not args.no_nd:
-        line["other_workloads"] = {name: nd_workload(pkg, torch, W, gen(**nd_kw)) for name, gen in nd_sets}
+        line["other_workloads"] = {name: nd_workload(pkg, torch, W, gen(**nd_kw), tune=not args.no_tune) for name, gen in nd_sets}
     if args.copy_calibration:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

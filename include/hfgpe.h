@@ -342,15 +342,43 @@ int hfgpe_stage_coeffs_coupled(const hfgpe_params *params, int ndim, const hfgpe
 int hfgpe_scheme_preset(const char *name, int *m, double *a, double *b);
 
 /* Pick the plan's schedule by timing candidates with HIP events on its
- * stream: for d-D plans the number of persistent workgroups per axis pass
- * (0 = sized per pass as for nd_workgroups = 0, or 256 ... 2048), for 1-D
- * plans the steps per resident launch (whole chunk, 1024 or 256; candidates
- * not shorter than trial_steps are skipped).  d_scratch is a device buffer of
- * the plan's layout holding representative data (its contents are
- * overwritten); trial_steps steps are run per candidate (>= 1).  The winning
- * setting is kept in the plan and written to *choice (may be NULL).
- * Synchronises the stream. */
+ * stream (the FFT passes of Sec. 2.1 cost the same arithmetic in every
+ * schedule; only how the pencils and steps are shared out changes, so the
+ * results do not depend on the choice -- bitwise in FP64).
+ *   d-D plans: the pass positions of a stage (the axis passes of
+ *     Eq. prod-genHarmOsc's stages, opening pass excluded) are tuned one
+ *     after another over the default policy, the persistent workgroups per
+ *     compute unit (1 .. 4, capped at what fits) and, for c64 separable
+ *     passes along strided axes that allow it, 256- or 512-thread groups;
+ *     each candidate is timed on min(trial_steps, 64) whole steps (the
+ *     positions tuned so far at their winners) after one untimed step.  The
+ *     winners are
+ *     kept in the plan (hfgpe_tune_get) and in a process-wide cache keyed by
+ *     grid shape, storage type, pass structure and position, from which
+ *     later plans of the same key start (hfgpe_tune_save / hfgpe_tune_load
+ *     carry it across processes).  nd_workgroups is set aside while tuning;
+ *     when non-zero it still overrides the tuned counts.  *choice = the
+ *     number of pass positions tuned.
+ *   1-D plans: the steps per resident launch (whole chunk, 1024 or 256;
+ *     candidates not shorter than trial_steps are skipped), trial_steps
+ *     steps each; *choice = the winner (0 = whole chunk).
+ * d_scratch is a device buffer of the plan's layout holding representative
+ * data (its contents are overwritten).  choice may be NULL.  Synchronises
+ * the stream. */
 int hfgpe_autotune(hfgpe_plan *plan, void *d_scratch, int64_t trial_steps, int *choice);
+
+/* The plan's launch settings of d-D pass position pass (0 .. *npasses - 1):
+ * workgroups per compute unit and threads per group, 0 meaning the default
+ * policy.  *npasses (may be NULL) receives the positions per stage (0 for 1-D
+ * plans); INVALID_ARG for a position out of range.  Host only. */
+int hfgpe_tune_get(const hfgpe_plan *plan, int pass, int *per_cu, int *tpb, int *npasses);
+
+/* Write the process-wide cache of tuned pass settings to a text file, or
+ * merge such a file into it (plans created afterwards start from it).  A
+ * malformed file is rejected whole (INVALID_ARG), as are unreadable paths.
+ * Host only; safe to call from several threads. */
+int hfgpe_tune_save(const char *path);
+int hfgpe_tune_load(const char *path);
 
 /* Device-side error word raised by the coefficient kernel since the last
  * call (0 or a status code); synchronises and clears it. */

@@ -31,7 +31,8 @@ SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", 
            "hfgpe_stage_coeffs_coupled", "hfgpe_set_potential", "hfgpe_set_stage_callback",
            "hfgpe_set_coef_callback",
            "hfgpe_scheme_preset",
-           "hfgpe_device_status", "hfgpe_profile", "hfgpe_autotune", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
+           "hfgpe_device_status", "hfgpe_profile", "hfgpe_autotune", "hfgpe_tune_get", "hfgpe_tune_save",
+           "hfgpe_tune_load", "hfgpe_status_string", "hfgpe_version", "hfgpe_last_hip_error"]
 
 
 class HfgpeError(RuntimeError):
@@ -126,6 +127,10 @@ def load() -> ctypes.CDLL:
     lib.hfgpe_device_status.argtypes = [vp]
     lib.hfgpe_profile.argtypes = [vp, dp, dp, i64p]
     lib.hfgpe_autotune.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int)]
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.hfgpe_tune_get.argtypes = [vp, ctypes.c_int, ip, ip, ip]
+    lib.hfgpe_tune_save.argtypes = [ctypes.c_char_p]
+    lib.hfgpe_tune_load.argtypes = [ctypes.c_char_p]
     lib.hfgpe_status_string.argtypes = [ctypes.c_int]
     lib.hfgpe_status_string.restype = ctypes.c_char_p
     lib.hfgpe_version.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -393,6 +398,19 @@ class Plan:
         _check(self.lib.hfgpe_autotune(self.handle, self._ptr(scratch), int(trial_steps),
                                        ctypes.byref(c)), "hfgpe_autotune")
         return c.value
+
+    def tune_settings(self):
+        """[(workgroups per CU, threads per group)] of every d-D pass position
+        (0 = the default policy); [] for 1-D plans."""
+        n = ctypes.c_int(0)
+        self.lib.hfgpe_tune_get(self.handle, -1, None, None, ctypes.byref(n))
+        out = []
+        for pp in range(n.value):
+            a, b = ctypes.c_int(0), ctypes.c_int(0)
+            _check(self.lib.hfgpe_tune_get(self.handle, pp, ctypes.byref(a), ctypes.byref(b), None),
+                   "hfgpe_tune_get")
+            out.append((a.value, b.value))
+        return out
 
     def device_status(self) -> int:
         return int(self.lib.hfgpe_device_status(self.handle))

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -43,6 +44,67 @@ int ilog2(int n)
     int l = 0;
     while ((1 << l) < n) ++l;
     return l;
+}
+
+// Launch settings of one d-D pass position: workgroups per CU and threads per
+// group (0: the default policy of launch_pass_tpb / nd_pass_threads).
+struct PassTune {
+    int per_cu = 0;
+    int tpb = 0;
+};
+
+// The axis passes of one stage, (axis, kind) in launch order.  Separable
+// trap: one pass per axis; coupled trap (non-separable drift): forward along
+// 0 .. d-2, forward + drift + inverse along d-1, inverse along d-2 .. 0.
+int stage_passes(int d, bool full, int *pax, int *pkind)
+{
+    int np = 0;
+    if (full) {
+        for (int j = 0; j < d - 1; ++j) { pax[np] = j; pkind[np++] = 1; }
+        pax[np] = d - 1; pkind[np++] = 2;
+        for (int j = d - 2; j >= 0; --j) { pax[np] = j; pkind[np++] = 3; }
+    } else {
+        for (int j = 0; j < d; ++j) { pax[np] = j; pkind[np++] = 0; }
+    }
+    return np;
+}
+
+// Process-wide cache of tuned pass settings, keyed by what decides a pass's
+// kernel instance and work: the grid shape, the storage type, the pass
+// structure (separable or coupled) and the pass position.  Plans created
+// later with the same key start from the tuned settings; hfgpe_tune_save /
+// hfgpe_tune_load carry the cache across processes as text.
+struct TuneKey {
+    int ndim, n0, n1, n2, c64, full, np, pp;
+    bool operator==(const TuneKey &o) const
+    {
+        return ndim == o.ndim && n0 == o.n0 && n1 == o.n1 && n2 == o.n2 && c64 == o.c64 && full == o.full &&
+               np == o.np && pp == o.pp;
+    }
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, PassTune>> g_tune_cache;
+
+void tune_cache_put(const TuneKey &k, const PassTune &v)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (auto &e : g_tune_cache)
+        if (e.first == k) {
+            e.second = v;
+            return;
+        }
+    g_tune_cache.emplace_back(k, v);
+}
+
+bool tune_cache_get(const TuneKey &k, PassTune &v)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (auto &e : g_tune_cache)
+        if (e.first == k) {
+            v = e.second;
+            return true;
+        }
+    return false;
 }
 
 struct Group1D {
@@ -93,6 +155,8 @@ struct hfgpe_plan {
     hipGraphExec_t graph_exec = nullptr;
     int graph_rec_steps = -1;
     int graph_grid = -1;
+    int graph_tune_gen = -1;
+    int tune_gen = 0;  // bumped whenever pass_tune changes
     void *graph_psi = nullptr;
     const double *graph_vi = nullptr;
     // caller's eps V_I per point (hfgpe_set_potential), or null
@@ -116,6 +180,9 @@ struct hfgpe_plan {
     int kin_nblk = 1;
     int nd_grid = 0;  // d-D persistent workgroups per pass; 0: per kernel instance
     int n_cu = 1;     // compute units of the plan's device
+    // d-D: tuned launch settings of each pass position within a stage (nd_step
+    // order); per_cu = 0 / tpb = 0 keep the default policy
+    std::vector<PassTune> pass_tune;
     int device = 0;   // the HIP device the plan was created on
     // profiling: (start, stop) event pairs recorded on the plan's stream
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_step, ev_coeff, ev_pool;
@@ -153,6 +220,21 @@ struct hfgpe_plan {
 };
 
 namespace {
+
+// The cache key of pass position pp of a d-D plan.
+TuneKey tune_key(const hfgpe_plan &P, int np, int pp)
+{
+    TuneKey k;
+    k.ndim = P.ndim;
+    k.n0 = P.insts[0].n[0];
+    k.n1 = P.insts[0].n[1];
+    k.n2 = P.insts[0].n[2];
+    k.c64 = P.dtype == HFGPE_C64 ? 1 : 0;
+    k.full = (P.coupled && P.scheme.rule != HFGPE_FSPLIT) ? 1 : 0;
+    k.np = np;
+    k.pp = pp;
+    return k;
+}
 
 TFunc to_tf(const hfgpe_tfunc &s)
 {
@@ -637,56 +719,61 @@ constexpr int kGraphSteps = 16;
 // Enqueue the m x d axis passes of one step (record row `step`, or the
 // device-side base + step when base is given).  profile: bracket each pass
 // with events (not allowed while capturing).
+// The launch of pass position pp of stage i: record row `step` (or the
+// device-side base + step), the opening x-phase on the first pass of an
+// evolve call, the closing one on the last pass of every stage, and the
+// plan's tuned settings for the position.
+static void nd_pass_launch(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const int *base, bool first, int i,
+                           int pp, const int *pax, const int *pkind, int np, LaunchND &L)
+{
+    const int m = P->m_eff;
+    const int j = pax[pp];
+    std::memset(&L, 0, sizeof(L));
+    L.insts = P->d_insts;
+    L.n_inst = P->n_inst;
+    L.rec = P->d_rec;
+    L.rec_open = P->d_rec_open;
+    L.recx = P->d_recx;
+    L.recx_open = P->d_recx_open;
+    L.kind = pkind[pp];
+    L.vi = P->d_vi;
+    L.vtab = P->d_vtab;
+    L.vtab_stride = P->vtab_stride;
+    L.cistab = P->d_cistab;
+    L.twtab = P->d_twtab;
+    L.twlog = P->twlog;
+    L.psi = d_psi;
+    L.c64 = P->dtype == HFGPE_C64;
+    L.ndim = P->ndim;
+    for (int a = 0; a < 3; ++a) L.n[a] = P->insts[0].n[a];
+    L.axis = j;
+    L.stage = i;
+    L.m = m;
+    L.rec_steps = rec_steps;
+    L.step = step;
+    L.step_base = base;
+    L.apply_open = (first && i == 0 && pp == 0) ? 1 : 0;
+    L.apply_close = (pp == np - 1) ? 1 : 0;
+    L.grid = P->nd_grid;
+    L.n_cu = P->n_cu;
+    L.generic = P->opts.nd_generic;
+    if (!L.apply_open && pp < (int)P->pass_tune.size()) {
+        L.per_cu = P->pass_tune[pp].per_cu;
+        L.tpb = P->pass_tune[pp].tpb;
+    }
+    L.stream = P->stream;
+}
+
 static int nd_step(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const int *base, bool first,
                    bool profile)
 {
-    const int m = P->m_eff, d = P->ndim;
-    // passes of one stage: (axis, kind); separable: one pass per axis; coupled
-    // (non-separable drift): forward along 0 .. d-2, forward + drift + inverse
-    // along d-1, inverse along d-2 .. 0
-    const bool full = P->coupled && P->scheme.rule != HFGPE_FSPLIT;
-    int pax[5], pkind[5], np = 0;
-    if (full) {
-        for (int j = 0; j < d - 1; ++j) { pax[np] = j; pkind[np++] = 1; }
-        pax[np] = d - 1; pkind[np++] = 2;
-        for (int j = d - 2; j >= 0; --j) { pax[np] = j; pkind[np++] = 3; }
-    } else {
-        for (int j = 0; j < d; ++j) { pax[np] = j; pkind[np++] = 0; }
-    }
+    const int m = P->m_eff;
+    int pax[5], pkind[5];
+    const int np = stage_passes(P->ndim, P->coupled && P->scheme.rule != HFGPE_FSPLIT, pax, pkind);
     for (int i = 0; i < m; ++i)
         for (int pp = 0; pp < np; ++pp) {
-            const int j = pax[pp];
             LaunchND L;
-            std::memset(&L, 0, sizeof(L));
-            L.insts = P->d_insts;
-            L.n_inst = P->n_inst;
-            L.rec = P->d_rec;
-            L.rec_open = P->d_rec_open;
-            L.recx = P->d_recx;
-            L.recx_open = P->d_recx_open;
-            L.kind = pkind[pp];
-            L.vi = P->d_vi;
-            L.vtab = P->d_vtab;
-            L.vtab_stride = P->vtab_stride;
-            L.cistab = P->d_cistab;
-            L.twtab = P->d_twtab;
-            L.twlog = P->twlog;
-            L.psi = d_psi;
-            L.c64 = P->dtype == HFGPE_C64;
-            L.ndim = P->ndim;
-            for (int a = 0; a < 3; ++a) L.n[a] = P->insts[0].n[a];
-            L.axis = j;
-            L.stage = i;
-            L.m = m;
-            L.rec_steps = rec_steps;
-            L.step = step;
-            L.step_base = base;
-            L.apply_open = (first && i == 0 && pp == 0) ? 1 : 0;
-            L.apply_close = (pp == np - 1) ? 1 : 0;
-            L.grid = P->nd_grid;
-            L.n_cu = P->n_cu;
-            L.generic = P->opts.nd_generic;
-            L.stream = P->stream;
+            nd_pass_launch(P, d_psi, rec_steps, step, base, first, i, pp, pax, pkind, np, L);
             std::pair<hipEvent_t, hipEvent_t> es{};
             const bool ev = profile && P->opts.profile;
             if (ev) {
@@ -708,7 +795,7 @@ static int nd_step(hfgpe_plan *P, void *d_psi, int rec_steps, int step, const in
 static int nd_graph_ready(hfgpe_plan *P, void *d_psi, int rec_steps)
 {
     if (P->graph_exec && P->graph_rec_steps == rec_steps && P->graph_grid == P->nd_grid && P->graph_psi == d_psi &&
-        P->graph_vi == P->d_vi)
+        P->graph_vi == P->d_vi && P->graph_tune_gen == P->tune_gen)
         return HFGPE_OK;
     if (P->graph_exec) {
         (void)hipGraphExecDestroy(P->graph_exec);
@@ -738,6 +825,7 @@ static int nd_graph_ready(hfgpe_plan *P, void *d_psi, int rec_steps)
     }
     P->graph_rec_steps = rec_steps;
     P->graph_grid = P->nd_grid;
+    P->graph_tune_gen = P->tune_gen;
     P->graph_psi = d_psi;
     P->graph_vi = P->d_vi;
     return HFGPE_OK;
@@ -1088,6 +1176,13 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
                 delete P;
                 return HFGPE_E_HIP;
             }
+        }
+        // tuned settings of the pass positions, when this shape has been tuned
+        {
+            int pax[5], pkind[5];
+            const int np = stage_passes(nd, P->coupled && S.rule != HFGPE_FSPLIT, pax, pkind);
+            P->pass_tune.assign(np, PassTune{});
+            for (int pp = 0; pp < np; ++pp) (void)tune_cache_get(tune_key(*P, np, pp), P->pass_tune[pp]);
         }
         ALLOC_TRY(P->d_graph_base, sizeof(int));
         {
@@ -1485,6 +1580,83 @@ int hfgpe_stage_coeffs_params(const hfgpe_params *params, int ndim, const hfgpe_
     return HFGPE_OK;
 }
 
+// d-D: tune the pass positions of a stage one after another (greedy
+// coordinate descent), each over the default policy, the workgroups per CU
+// (1 .. 4, capped at what fits) and, for c64 separable passes along strided
+// axes that allow it, 256- or 512-thread groups.  A candidate is timed on
+// whole steps -- every pass of the step, the positions already tuned at their
+// winners -- since a pass's speed depends on what its neighbours leave in the
+// caches.  Each candidate runs `reps` steps after one untimed step, between
+// HIP events on the plan's stream.  Results are bitwise the same for every
+// candidate: they change how the pencils are shared out, not what is computed
+// for a pencil.
+static int autotune_nd(hfgpe_plan *P, void *d_scratch, int reps)
+{
+    // records of a one-step chunk (rec_steps = 1, row 0) for the trial steps
+    int rc = hfgpe_evolve(P, d_scratch, 0.0, 1);
+    if (rc) return rc;
+    int pax[5], pkind[5];
+    const int np = stage_passes(P->ndim, P->coupled && P->scheme.rule != HFGPE_FSPLIT, pax, pkind);
+    P->pass_tune.assign(np, PassTune{});
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return HFGPE_E_HIP;
+    }
+    const int saved_grid = P->nd_grid;
+    P->nd_grid = 0;  // per-pass sizing
+    for (int pp = 0; pp < np && rc == HFGPE_OK; ++pp) {
+        const int axis = pax[pp];
+        const int *n = P->insts[0].n;
+        std::vector<PassTune> cand{PassTune{}};  // the default policy first
+        std::vector<int> tpbs{0};
+        if (P->dtype == HFGPE_C64 && pkind[pp] == 0 && axis > 0 && points_per_thread_nd(n[axis]) == 8 &&
+            nd_group_log(n, axis, 512) > nd_group_log(n, axis, 256))
+            tpbs = {256, 512};
+        for (int tpb : tpbs)
+            for (int per_cu = 1; per_cu <= 4; ++per_cu) {
+                PassTune c;
+                c.per_cu = per_cu;
+                c.tpb = tpb;
+                cand.push_back(c);
+            }
+        float best = 0.0f;
+        PassTune best_t;
+        for (size_t ci = 0; ci < cand.size() && rc == HFGPE_OK; ++ci) {
+            P->pass_tune[pp] = cand[ci];
+            rc = nd_step(P, d_scratch, 1, 0, nullptr, false, false);  // untimed
+            hipError_t e = rc ? hipSuccess : hipEventRecord(e0, P->stream);
+            for (int r = 0; r < reps && rc == HFGPE_OK && e == hipSuccess; ++r)
+                rc = nd_step(P, d_scratch, 1, 0, nullptr, false, false);
+            if (rc) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, P->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                g_last_hip_error = (int)e;
+                rc = HFGPE_E_HIP;
+                break;
+            }
+            if (ci == 0 || ms < best) {
+                best = ms;
+                best_t = cand[ci];
+            }
+        }
+        P->pass_tune[pp] = best_t;
+    }
+    if (rc == HFGPE_OK)
+        for (int pp = 0; pp < np; ++pp) tune_cache_put(tune_key(*P, np, pp), P->pass_tune[pp]);
+    else
+        P->pass_tune.assign(np, PassTune{});
+    P->nd_grid = saved_grid;
+    P->tune_gen += 1;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 int hfgpe_autotune(hfgpe_plan *P, void *d_scratch, int64_t trial_steps, int *choice)
 {
     if (!P || trial_steps < 1) return HFGPE_E_INVALID_ARG;
@@ -1492,26 +1664,19 @@ int hfgpe_autotune(hfgpe_plan *P, void *d_scratch, int64_t trial_steps, int *cho
         if (choice) *choice = 0;
         return HFGPE_OK;
     }
-    if (!d_scratch) return HFGPE_E_INVALID_ARG;
-    // candidate schedules
-    std::vector<int> cand;
-    int64_t groups = 0;
+    if (!d_scratch || !state_aligned(P, d_scratch)) return HFGPE_E_INVALID_ARG;
+    const int saved_profile = P->opts.profile;
+    P->opts.profile = 0;
     if (P->ndim > 1) {
-        int64_t pts = P->offsets[1];
-        for (int j = 0; j < P->ndim; ++j)
-            groups = std::max<int64_t>(groups, (int64_t)P->n_inst * ((pts / P->insts[0].n[j]) >>
-                                                                    nd_group_log(P->insts[0].n, j, 256)));
-        cand.push_back(0);  // per kernel instance: occupancy x compute units
-        for (int g : {256, 512, 768, 1024, 1536, 2048})
-            if (g <= groups) cand.push_back(g);
-        if (cand.size() == 1) cand.push_back((int)groups);
-    } else {
-        // steps per resident launch: the whole chunk (0) or shorter launches
-        for (int64_t k : {(int64_t)0, (int64_t)1024, (int64_t)256})
-            if (k == 0 || k < trial_steps) cand.push_back((int)k);
+        int rc = autotune_nd(P, d_scratch, (int)std::min<int64_t>(trial_steps, 64));
+        P->opts.profile = saved_profile;
+        if (choice) *choice = (int)P->pass_tune.size();
+        return rc;
     }
-    std::sort(cand.begin(), cand.end());
-    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    // 1-D: steps per resident launch, the whole chunk (0) or shorter launches
+    std::vector<int> cand;
+    for (int64_t k : {(int64_t)0, (int64_t)1024, (int64_t)256})
+        if (k == 0 || k < trial_steps) cand.push_back((int)k);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     {
@@ -1519,17 +1684,15 @@ int hfgpe_autotune(hfgpe_plan *P, void *d_scratch, int64_t trial_steps, int *cho
         if (e != hipSuccess) {
             g_last_hip_error = (int)e;
             (void)hipEventDestroy(e0);
+            P->opts.profile = saved_profile;
             return HFGPE_E_HIP;
         }
     }
-    const int saved_profile = P->opts.profile;
-    P->opts.profile = 0;
     float best = 0.0f;
     int best_c = cand[0];
     int rc = HFGPE_OK;
     for (size_t ci = 0; ci < cand.size() && rc == HFGPE_OK; ++ci) {
-        if (P->ndim > 1) P->nd_grid = cand[ci];
-        else P->opts.steps_per_launch = cand[ci];
+        P->opts.steps_per_launch = cand[ci];
         rc = hfgpe_evolve(P, d_scratch, 0.0, 1);  // warm up this configuration
         if (rc) break;
         if (hipEventRecord(e0, P->stream) != hipSuccess) { rc = HFGPE_E_HIP; break; }
@@ -1549,10 +1712,66 @@ int hfgpe_autotune(hfgpe_plan *P, void *d_scratch, int64_t trial_steps, int *cho
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     P->opts.profile = saved_profile;
-    if (P->ndim > 1) P->nd_grid = best_c;
-    else P->opts.steps_per_launch = best_c;
+    P->opts.steps_per_launch = best_c;
     if (choice) *choice = best_c;
     return rc;
+}
+
+int hfgpe_tune_get(const hfgpe_plan *P, int pp, int *per_cu, int *tpb, int *npasses)
+{
+    if (!P) return HFGPE_E_INVALID_ARG;
+    if (npasses) *npasses = (int)P->pass_tune.size();
+    if (pp < 0 || pp >= (int)P->pass_tune.size()) return HFGPE_E_INVALID_ARG;
+    if (per_cu) *per_cu = P->pass_tune[pp].per_cu;
+    if (tpb) *tpb = P->pass_tune[pp].tpb;
+    return HFGPE_OK;
+}
+
+int hfgpe_tune_save(const char *path)
+{
+    if (!path) return HFGPE_E_INVALID_ARG;
+    std::vector<std::pair<TuneKey, PassTune>> snap;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        snap = g_tune_cache;
+    }
+    FILE *f = std::fopen(path, "w");
+    if (!f) return HFGPE_E_INVALID_ARG;
+    bool ok = std::fprintf(f, "# hfgpe pass tuning v1: ndim n0 n1 n2 c64 coupled npasses pass per_cu tpb\n") > 0;
+    for (const auto &e : snap) {
+        const TuneKey &k = e.first;
+        ok = ok && std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d\n", k.ndim, k.n0, k.n1, k.n2, k.c64, k.full, k.np,
+                                k.pp, e.second.per_cu, e.second.tpb) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? HFGPE_OK : HFGPE_E_INVALID_ARG;
+}
+
+int hfgpe_tune_load(const char *path)
+{
+    if (!path) return HFGPE_E_INVALID_ARG;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return HFGPE_E_INVALID_ARG;
+    std::vector<std::pair<TuneKey, PassTune>> rows;
+    char line[256];
+    int rc = HFGPE_OK;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        TuneKey k;
+        PassTune v;
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d", &k.ndim, &k.n0, &k.n1, &k.n2, &k.c64, &k.full, &k.np,
+                        &k.pp, &v.per_cu, &v.tpb) != 10 ||
+            k.ndim < 2 || k.ndim > 3 || k.np < 1 || k.np > 5 || k.pp < 0 || k.pp >= k.np || v.per_cu < 0 ||
+            v.per_cu > 64 || (v.tpb != 0 && v.tpb != 256 && v.tpb != 512)) {
+            rc = HFGPE_E_INVALID_ARG;
+            break;
+        }
+        rows.emplace_back(k, v);
+    }
+    std::fclose(f);
+    if (rc) return rc;  // nothing taken from a malformed file
+    for (const auto &r : rows) tune_cache_put(r.first, r.second);
+    return HFGPE_OK;
 }
 
 int hfgpe_profile(hfgpe_plan *P, double *step_ms, double *coeff_ms, int64_t *step_launches)

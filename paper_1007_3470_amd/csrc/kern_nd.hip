@@ -119,7 +119,7 @@ static hipError_t launch_pass_mode(const LaunchND &L)
     switch (L.kind) {
     case kPassSep:
         if constexpr (P == 8 && sizeof(Store) == 8) {
-            if (nd_threads(L.n, L.axis, 1) == 512) return launch_pass_tpb<Store, P, MAXS, MODE, 512, kPassSep, 0>(L);
+            if (nd_pass_threads(L) == 512) return launch_pass_tpb<Store, P, MAXS, MODE, 512, kPassSep, 0>(L);
         }
         return launch_pass_tpb<Store, P, MAXS, MODE, kThreadsND, kPassSep, 0>(L);
     case kPassFwd:
@@ -170,11 +170,18 @@ hipError_t launch_nd_pass(const LaunchND &L)
     return L.c64 ? launch_pass_store<float2>(L) : launch_pass_store<double2>(L);
 }
 
-// Threads per workgroup of a pass: 512 only for the separable c64 passes that
-// nd_threads selects, 256 otherwise.
+// Threads per workgroup of a pass: 512 only for separable c64 passes along a
+// strided axis with 8 points per thread whose 512-thread group holds more
+// pencils than a 256-thread one -- by default where nd_threads selects it, or
+// as a tuned choice (L.tpb); 256 otherwise.
 int nd_pass_threads(const LaunchND &L)
 {
-    return (L.kind == kPassSep && L.c64) ? nd_threads(L.n, L.axis, 1) : kThreadsND;
+    if (L.kind != kPassSep || !L.c64) return kThreadsND;
+    if (L.tpb == kThreadsND) return kThreadsND;
+    if (L.tpb == 512 && L.axis > 0 && points_per_thread_nd(L.n[L.axis]) == 8 &&
+        nd_group_log(L.n, L.axis, 512) > nd_group_log(L.n, L.axis, kThreadsND))
+        return 512;
+    return nd_threads(L.n, L.axis, 1);
 }
 
 // A pass runs a fixed-shape instance when its axis has 128 .. 1024 points and

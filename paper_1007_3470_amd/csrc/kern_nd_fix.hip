@@ -37,7 +37,7 @@ static hipError_t launch_fix_tpb(const LaunchND &L)
 {
     if constexpr (sizeof(Store) == 8) {
         // 512-thread groups only for c64 strided axes with short rows
-        if (nd_threads(L.n, L.axis, 1) == 512) {
+        if (nd_pass_threads(L) == 512) {
             if (L.axis == 0) return hipErrorInvalidValue;
             switch (L.n[L.axis]) {
             case 128: return launch_pass_tpb<Store, 8, 1, MODE, 512, kPassSep, 2 * 7 + 1>(L);

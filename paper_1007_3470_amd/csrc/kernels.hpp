@@ -110,6 +110,8 @@ struct LaunchND {
     int grid;     // persistent workgroups; 0: as many as the device holds at once for the pass's kernel
     int n_cu;     // compute units of the device
     int generic;  // 1: runtime-shaped FFT for every axis length
+    int per_cu;   // with grid = 0: workgroups per CU (capped by what fits); 0: the default policy
+    int tpb;      // threads per group, 256 or 512 (c64 separable strided passes only); 0: default
     hipStream_t stream;
 };
 hipError_t launch_nd_pass(const LaunchND &L);

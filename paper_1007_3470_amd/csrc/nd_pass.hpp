@@ -418,8 +418,13 @@ hipError_t launch_pass_tpb(const LaunchND &L)
             per_cu = per_cu > 0 ? per_cu : 1;
             if (FIX != 0) fixed_per_cu.store(per_cu, std::memory_order_relaxed);
         }
-        if ((L.axis == 0 || ((1 << lG) * (int)sizeof(Store)) < 64) && per_cu > 2) per_cu = 2;
-        if (per_cu > 3) per_cu = 3;
+        if (L.per_cu > 0) {
+            // a tuned count, never more than fit at once
+            per_cu = per_cu < L.per_cu ? per_cu : L.per_cu;
+        } else {
+            if ((L.axis == 0 || ((1 << lG) * (int)sizeof(Store)) < 64) && per_cu > 2) per_cu = 2;
+            if (per_cu > 3) per_cu = 3;
+        }
         const int64_t pts = (int64_t)L.n[0] * L.n[1] * L.n[2];
         const int64_t groups = (int64_t)L.n_inst * ((pts / L.n[L.axis]) >> lG);
         const int64_t want = (int64_t)per_cu * (L.n_cu > 0 ? L.n_cu : 1);

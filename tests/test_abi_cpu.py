@@ -321,3 +321,21 @@ def test_modulation_validation():
     assert _create([replace(cpl, wmod=((0.5, 0.0, 0.0, 2),) + cpl.wmod[1:])], rule="cf4") == -1   # pulse freq 0
     assert _create([replace(base, vmod=(float("inf"), 1.0, 0.0, 0))]) == -1
     assert _gpu_or_nodevice(_create([replace(base, vmod=(0.5, 1.0, 0.0, 2))]))
+
+
+def test_tune_cache_save_load(tmp_path):
+    """The pass-tuning cache round-trips through its text form; a malformed
+    file is rejected whole."""
+    lib = pkg.load()
+    good = tmp_path / "tune.txt"
+    good.write_text("# comment\n2 512 512 1 1 0 2 0 2 256\n2 512 512 1 1 0 2 1 3 512\n")
+    assert lib.hfgpe_tune_load(str(good).encode()) == 0
+    out = tmp_path / "out.txt"
+    assert lib.hfgpe_tune_save(str(out).encode()) == 0
+    rows = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert "2 512 512 1 1 0 2 0 2 256" in rows and "2 512 512 1 1 0 2 1 3 512" in rows
+    bad = tmp_path / "bad.txt"
+    bad.write_text("2 512 512 1 1 0 2 0 2 256\n2 512 512 1 1 0 2 5 2 256\n")   # position 5 of 2
+    assert lib.hfgpe_tune_load(str(bad).encode()) == -1
+    assert lib.hfgpe_tune_load(str(tmp_path / "missing.txt").encode()) == -1
+    assert lib.hfgpe_tune_save(None) == -1

@@ -184,20 +184,32 @@ def test_graph_3d_ni5_matches_oracle(pkg):
     assert W.rel_l2(got[0], ref) < 1e-11
 
 
-def test_autotune_keeps_results(pkg):
+@pytest.mark.parametrize("make", [lambda: W.gpe_2d(n=512, n_inst=2, nsteps=12),
+                                  lambda: W.gpe_3d(n=128, nsteps=3),
+                                  lambda: W.coupled_2d(n=256, n_inst=2, nsteps=4)],
+                         ids=["2d_512", "3d_128", "coupled_2d_256"])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_autotune_keeps_results(pkg, make, dtype):
+    """The per-pass tuner (workgroups per CU, 256/512-thread groups) changes
+    how pencils are shared out, not their arithmetic: bitwise the default
+    results, direct and replayed from a graph captured after tuning."""
     import torch
-    w = W.gpe_2d(n=128, n_inst=4, nsteps=12)
-    _, _, ref = run_gpu(pkg, w, "c128")
-    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, "c128", w.dt)
-    choice = plan.autotune(w.psi0, trial_steps=4)
-    say("autotune chose %d workgroups (0: sized per pass)" % choice)
-    assert choice >= 0
+    w = make()
+    _, _, ref = run_gpu(pkg, w, dtype)
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, use_graph=True)
+    n = plan.autotune(w.psi0, trial_steps=3)
+    tuned = plan.tune_settings()
+    say("autotune %s: %d pass positions -> %s" % (dtype, n, tuned))
+    assert n == len(tuned) > 0 and all(0 <= pc <= 4 and tpb in (0, 256, 512) for pc, tpb in tuned)
     buf = plan.pack(w.psi0)
     plan.evolve(buf, w.t0, w.nsteps)
     torch.cuda.synchronize()
     got = plan.unpack(buf)
-    for k in range(4):
+    for k in range(len(w.instances)):
         assert np.array_equal(got[k], ref[k])
+    # a new plan of the same shape starts from the process-wide cache
+    again = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt)
+    assert again.tune_settings() == tuned
 
 
 @pytest.mark.parametrize("make", [lambda: W.gpe_3d(n=128, nsteps=3),
