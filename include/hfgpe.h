@@ -88,7 +88,9 @@ typedef enum {
 /* Largest number of sub-steps of the HFGPE_HO_FUNDAMENTAL rule. */
 #define HFGPE_MAX_HO_SUBSTEPS 256
 
-/* Uniform periodic grid of one instance. */
+/* Uniform periodic grid of one instance: the equidistant nodes
+ * x_{j,i} = lo_j + i (hi_j - lo_j)/n_j of the Fourier collocation of
+ * Eq. GP1ODE (Sec. 1), on which the state is the vector of point values. */
 typedef struct {
     int ndim;      /* 1, 2 or 3 */
     int n[3];      /* points per axis, powers of two; axes >= ndim must be 1 */
@@ -205,7 +207,9 @@ typedef struct {
 
 typedef struct hfgpe_plan hfgpe_plan;
 
-/* Create a plan for n_inst independent instances (n_inst >= 0; 0 gives an
+/* Create a plan for n_inst independent instances of the problem of Sec. 1
+ * (Eq. GP1 with the harmonic part of Eq. GP1b), advanced by the composition
+ * of Eq. prod-gen with the HO split (ii) of Sec. 2.1 (n_inst >= 0; 0 gives an
  * empty plan whose calls do nothing).  grids and params are host arrays of
  * n_inst entries, copied into the plan.  All instances share the scheme, the
  * dtype, the step dt (may be negative) and the spatial dimension.
@@ -226,7 +230,11 @@ int hfgpe_plan_destroy(hfgpe_plan *plan);
 int hfgpe_instance_offsets(const hfgpe_plan *plan, int64_t *off);
 
 /* Advance every instance nsteps steps of size dt from time t0, in place on
- * the device buffer d_psi (layout above).  Stream-ordered and asynchronous:
+ * the device buffer d_psi (layout above).  A step is the composition of
+ * Table "algorithm" (time frozen in the B flows at the stage times) with each
+ * A stage factored as chirp, kinetic phase, chirp (Lemma 2, Theorems 1 and
+ * 2), adjacent x-space phases merged as in Eq. prod-genHarmOsc: m FFT pairs
+ * per step (per axis for d-D).  Stream-ordered and asynchronous:
  * the call returns once the work is enqueued.  On return of the enqueued
  * work d_psi holds the state at t0 + nsteps*dt with no pending merged phase.
  * nsteps = 0 does nothing. */
@@ -305,7 +313,9 @@ int hfgpe_norm(hfgpe_plan *plan, const void *d_psi, double *h_out);
  * buffers. */
 int hfgpe_norm_noalloc(hfgpe_plan *plan, const void *d_psi, double *d_out);
 
-/* GPE energy of every instance at time t into h_out[4*n_inst]:
+/* GPE energy of every instance at time t into h_out[4*n_inst] (Sec. 1 names
+ * the energy but prints no functional; this is the standard GPE energy, whose
+ * interaction term carries sigma/2 so that its variation gives the equation):
  * (total, kinetic, potential, interaction) per instance, with
  *   kinetic     = h^d / N sum_k |k|^2 / (2 mu) |u^_k|^2,
  *   potential   = h^d sum_x ((mu/2) x^T W(t) x + eps V_I) |u|^2, with
