@@ -188,7 +188,8 @@ typedef struct {
                               stream then runs on a blocking stream of its own,
                               ordered against the default stream) */
     int profile;           /* 1 = bracket every step-kernel launch with HIP
-                              events on the plan's stream (hfgpe_profile) */
+                              events on the plan's stream (hfgpe_profile);
+                              2 = also every coefficient-kernel launch */
     int nd_workgroups;     /* d-D: persistent workgroups per axis pass (0 =
                               per pass, as many as the device holds at once:
                               at most 3 per CU, 2 along x and for strided rows
@@ -285,6 +286,14 @@ int hfgpe_set_coef_callback(hfgpe_plan *plan, hfgpe_coef_fn fn, void *user);
  * chunk into LDS).  Errors: INVALID_ARG (plan NULL, or d_vi not aligned to 8
  * bytes). */
 int hfgpe_set_potential(hfgpe_plan *plan, const double *d_vi);
+
+/* The same with eps V_I held in FP32 (4 bytes per point: half the extra bytes
+ * of the passes that apply the x-space phase).  The values enter the FP64
+ * phase as they are, so the potential carries its FP32 rounding (~6e-8
+ * relative), which the caller accepts by choosing this form.  Setting either
+ * form replaces the other; NULL restores the factor form.  Errors:
+ * INVALID_ARG (plan NULL, or d_vi not aligned to 4 bytes). */
+int hfgpe_set_potential_f32(hfgpe_plan *plan, const float *d_vi);
 
 /* Discrete squared norm h^d sum |u|^2 of every instance into the host array
  * h_out[n_inst] (FP64, compensated summation): the norm that the GPE and its
@@ -395,8 +404,9 @@ int hfgpe_tune_load(const char *path);
 int hfgpe_device_status(hfgpe_plan *plan);
 
 /* With opts.profile set: total milliseconds spent in the step kernels and
- * in the coefficient kernel, and the number of step-kernel launches, since
- * the last call (synchronises the stream; resets the counters). */
+ * (profile level 2) in the coefficient kernel, and the number of step-kernel
+ * launches, since the last call (synchronises the stream; resets the
+ * counters). */
 int hfgpe_profile(hfgpe_plan *plan, double *step_ms, double *coeff_ms, int64_t *step_launches);
 
 const char *hfgpe_status_string(int status);

@@ -28,7 +28,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported grid shape", -3: "si
           -7: "non-finite coefficient", -8: "no gfx950 device"}
 SYMBOLS = ["hfgpe_plan_create", "hfgpe_plan_destroy", "hfgpe_instance_offsets", "hfgpe_evolve",
            "hfgpe_norm", "hfgpe_norm_noalloc", "hfgpe_energy", "hfgpe_stage_coeffs", "hfgpe_stage_coeffs_params",
-           "hfgpe_stage_coeffs_coupled", "hfgpe_set_potential", "hfgpe_set_stage_callback",
+           "hfgpe_stage_coeffs_coupled", "hfgpe_set_potential", "hfgpe_set_potential_f32", "hfgpe_set_stage_callback",
            "hfgpe_set_coef_callback",
            "hfgpe_scheme_preset",
            "hfgpe_device_status", "hfgpe_profile", "hfgpe_autotune", "hfgpe_tune_get", "hfgpe_tune_save",
@@ -113,6 +113,7 @@ def load() -> ctypes.CDLL:
     lib.hfgpe_norm.argtypes = [vp, vp, dp]
     lib.hfgpe_norm_noalloc.argtypes = [vp, vp, vp]
     lib.hfgpe_set_potential.argtypes = [vp, vp]
+    lib.hfgpe_set_potential_f32.argtypes = [vp, vp]
     lib.hfgpe_set_stage_callback.argtypes = [vp, STAGE_FN, vp]
     lib.hfgpe_set_coef_callback.argtypes = [vp, COEF_FN, vp]
     lib.hfgpe_energy.argtypes = [vp, vp, ctypes.c_double, dp]
@@ -233,7 +234,7 @@ class Plan:
 
     def __init__(self, instances: Sequence, scheme: str = "leapfrog", ho_rule: str = "cf4",
                  dtype: str = "c128", dt: float = 1e-3, steps_per_launch: int = 0,
-                 plain: bool = False, use_graph: bool = False, profile: bool = False,
+                 plain: bool = False, use_graph: bool = False, profile: int = 0,
                  nd_workgroups: int = 0, nd_generic: bool = False, chunk_steps: int = 0, stream=None,
                  a: Optional[Sequence[float]] = None, b: Optional[Sequence[float]] = None):
         import torch
@@ -249,7 +250,7 @@ class Plan:
         grids = (Grid * max(1, self.n_inst))(*[make_grid(i) for i in instances])
         params = (Params * max(1, self.n_inst))(*[make_params(i) for i in instances])
         opts = Options(int(steps_per_launch), int(bool(plain)), int(bool(use_graph)),
-                       int(bool(profile)), int(nd_workgroups), int(bool(nd_generic)), int(chunk_steps))
+                       int(profile), int(nd_workgroups), int(bool(nd_generic)), int(chunk_steps))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -345,14 +346,20 @@ class Plan:
         _check(self.lib.hfgpe_set_coef_callback(self.handle, self._coef_cb, None), "hfgpe_set_coef_callback")
 
     def set_potential(self, vi) -> None:
-        """Use a device tensor of eps V_I per point (float64, the state's packed
-        layout) instead of the factor form; None restores it.  The tensor is
-        kept referenced by the plan."""
+        """Use a device tensor of eps V_I per point (float64 or float32, the
+        state's packed layout) instead of the factor form; None restores it.
+        The tensor is kept referenced by the plan."""
         if vi is None:
             self._vi = None
             _check(self.lib.hfgpe_set_potential(self.handle, None), "hfgpe_set_potential")
             return
         import torch
+        if vi.dtype == torch.float32:
+            _check_device_buffer(vi, torch.float32, int(self.offsets[-1]), "potential")
+            self._vi = vi
+            _check(self.lib.hfgpe_set_potential_f32(self.handle, ctypes.c_void_p(vi.data_ptr())),
+                   "hfgpe_set_potential_f32")
+            return
         _check_device_buffer(vi, torch.float64, int(self.offsets[-1]), "potential")
         self._vi = vi
         _check(self.lib.hfgpe_set_potential(self.handle, ctypes.c_void_p(vi.data_ptr())),

@@ -26,6 +26,9 @@ struct Fge {
 // the modulated quantity before the kind's final square root
 __host__ __device__ inline double tf_inner(const TFunc &m, double t)
 {
+    // a constant form: v0 exactly, as v0 (1 + 0 * ...) would give, without the
+    // transcendental
+    if (m.amp == 0.0) return m.v0;
     if (m.kind == 2) {
         const double c = cosh(m.freq * (t - m.phase));
         return m.v0 * (1.0 + m.amp * t / (c * c));

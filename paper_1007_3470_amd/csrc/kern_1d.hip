@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kThreads1D, (P <= 8 ? 2 : 1)) void hf1d_kernel(cons
                                                           const Rec *__restrict__ rec,
                                                           const Rec *__restrict__ rec_open,
                                                           const double2 *__restrict__ cistab,
-                                                          const double *__restrict__ vi,
+                                                          const void *__restrict__ vi, int vi_f32,
                                                           Store *__restrict__ psi, int m, int K,
                                                           int rec_steps, int step_base,
                                                           int apply_opening)
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kThreads1D, (P <= 8 ? 2 : 1)) void hf1d_kernel(cons
     for (int c = 0; c < P; ++c) {
         int i = tl + c * T;
         double x = lo + (double)i * dx;
-        ve[i] = vi ? vi[I.offset + i] : eps * vfactor(vf, x);
+        ve[i] = vi ? vi_at(vi, vi_f32, I.offset + i) : eps * vfactor(vf, x);
         u[c] = active ? to_d2(base[i]) : make_double2(0.0, 0.0);
     }
     __syncthreads();  // cis table in LDS
@@ -118,7 +118,7 @@ template <typename Store, int LOGN>
 __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__restrict__ perm,
                                                 const InstDev *__restrict__ insts, const Rec *__restrict__ rec,
                                                 const Rec *__restrict__ rec_open, const CisTable &ctab,
-                                                const double *__restrict__ vi, double2 *lds, double *vel,
+                                                const void *__restrict__ vi, int vi_f32, double2 *lds, double *vel,
                                                 Store *__restrict__ psi, int m,
                                                 int K, int rec_steps, int step_base, int apply_opening)
 {
@@ -143,7 +143,7 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
     for (int c = 0; c < P; ++c) {
         const int i = tl + c * T;
         const double x = lo + (double)i * dx;
-        ve[c * T] = vi ? vi[I.offset + i] : eps * vfactor(vf, x);
+        ve[c * T] = vi ? vi_at(vi, vi_f32, I.offset + i) : eps * vfactor(vf, x);
         u[c] = active ? to_d2(base[i]) : make_double2(0.0, 0.0);
     }
     __syncthreads();  // cis table in LDS
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kThreads1D, 2) void hf1d_fixed_kernel(const Item1D 
                                                                 const Rec *__restrict__ rec,
                                                                 const Rec *__restrict__ rec_open,
                                                                 const double2 *__restrict__ cistab,
-                                                                const double *__restrict__ vi,
+                                                                const void *__restrict__ vi, int vi_f32,
                                                                 Store *__restrict__ psi, int m, int K,
                                                                 int rec_steps, int step_base, int apply_opening)
 {
@@ -206,12 +206,12 @@ __global__ __launch_bounds__(kThreads1D, 2) void hf1d_fixed_kernel(const Item1D 
     load_cis_table(&ctab, cistab);
     const Item1D it = items[blockIdx.x];
     switch (it.logn) {
-    case 6: hf1d_fixed_body<Store, 6>(it, perm, insts, rec, rec_open, ctab, vi, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 7: hf1d_fixed_body<Store, 7>(it, perm, insts, rec, rec_open, ctab, vi, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 8: hf1d_fixed_body<Store, 8>(it, perm, insts, rec, rec_open, ctab, vi, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 9: hf1d_fixed_body<Store, 9>(it, perm, insts, rec, rec_open, ctab, vi, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 10: hf1d_fixed_body<Store, 10>(it, perm, insts, rec, rec_open, ctab, vi, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 11: hf1d_fixed_body<Store, 11>(it, perm, insts, rec, rec_open, ctab, vi, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
+    case 6: hf1d_fixed_body<Store, 6>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
+    case 7: hf1d_fixed_body<Store, 7>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
+    case 8: hf1d_fixed_body<Store, 8>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
+    case 9: hf1d_fixed_body<Store, 9>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
+    case 10: hf1d_fixed_body<Store, 10>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
+    case 11: hf1d_fixed_body<Store, 11>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
     default: break;  // the launcher sends only 64 <= N <= 2048 here
     }
 }
@@ -308,7 +308,7 @@ template <typename Store, typename Xch, int P, int MAXS>
 static hipError_t launch_p(const Launch1D &L)
 {
     hipLaunchKernelGGL((hf1d_kernel<Store, Xch, P, MAXS>), dim3(L.n_items), dim3(kThreads1D), 0, L.stream,
-                       L.items, L.perm, L.insts, L.rec, L.rec_open, L.cistab, L.vi, (Store *)L.psi, L.m, L.K,
+                       L.items, L.perm, L.insts, L.rec, L.rec_open, L.cistab, L.vi, L.vi_f32, (Store *)L.psi, L.m, L.K,
                        L.rec_steps, L.step_base, L.apply_opening);
     return hipGetLastError();
 }
@@ -319,7 +319,7 @@ static hipError_t launch_store(const Launch1D &L)
     if (L.fixed) {
         if (L.P != 8) return hipErrorInvalidValue;
         hipLaunchKernelGGL((hf1d_fixed_kernel<Store>), dim3(L.n_items), dim3(kThreads1D), 0, L.stream, L.items,
-                           L.perm, L.insts, L.rec, L.rec_open, L.cistab, L.vi, (Store *)L.psi, L.m, L.K,
+                           L.perm, L.insts, L.rec, L.rec_open, L.cistab, L.vi, L.vi_f32, (Store *)L.psi, L.m, L.K,
                            L.rec_steps, L.step_base, L.apply_opening);
         return hipGetLastError();
     }

@@ -27,17 +27,26 @@ __device__ __forceinline__ void raise_err(int *err, int code)
 }
 
 // One instantiation per (HO rule, dimension): the stage loop over axes
-// unrolls and the per-axis coefficients stay in registers.
+// unrolls and the per-axis coefficients stay in registers.  Consecutive
+// threads take consecutive steps of an instance, so the first-stage
+// coefficients of step n + 1, which the merge at the end of step n needs, are
+// taken from the neighbouring thread through LDS (the same values it would
+// compute) instead of being evaluated twice.
+constexpr int kCoeffThreads = 128;
+
 template <int RULE, int ND>
-__global__ __launch_bounds__(128) void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
-                                                    const SchemeDev *__restrict__ sch, Rec *__restrict__ rec,
-                                                    Rec *__restrict__ rec_open, double t0, double dt,
-                                                    int64_t step0, int k_steps, int64_t nsteps_total, int *err)
+__global__ __launch_bounds__(kCoeffThreads) void coeff_kernel(const InstDev *__restrict__ insts, int n_inst,
+                                                              const SchemeDev *__restrict__ sch,
+                                                              Rec *__restrict__ rec, Rec *__restrict__ rec_open,
+                                                              double t0, double dt, int64_t step0, int k_steps,
+                                                              int64_t nsteps_total, int *err)
 {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)n_inst * k_steps) return;
-    const int inst = (int)(idx / k_steps);
-    const int s = (int)(idx % k_steps);
+    __shared__ double first_e[ND][kCoeffThreads];  // e of stage 0 of each thread's step
+    const int64_t total = (int64_t)n_inst * k_steps;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = idx < total;
+    const int inst = active ? (int)(idx / k_steps) : 0;
+    const int s = active ? (int)(idx % k_steps) : 0;
     const InstDev &I = insts[inst];
     const int m = sch->m, substeps = sch->substeps;
     const double mu = I.mu;
@@ -51,9 +60,14 @@ __global__ __launch_bounds__(128) void coeff_kernel(const InstDev *__restrict__ 
     Fge cur[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) {
-        cur[j] = fge_stage_t<RULE>(mu, I.om[j], tn, dt * sch->a[0], substeps);
+        cur[j] = active ? fge_stage_t<RULE>(mu, I.om[j], tn, dt * sch->a[0], substeps) : Fge{0.0, 0.0, 0.0, 0};
         status = status ? status : cur[j].status;
+        first_e[j][threadIdx.x] = cur[j].e;
     }
+    __syncthreads();
+    // the neighbour holds step n + 1 of the same instance
+    const bool have_next = threadIdx.x + 1 < blockDim.x && idx + 1 < total && s + 1 < k_steps;
+    if (!active) return;
     if (n == 0) {
         Rec o;
 #pragma unroll
@@ -93,9 +107,15 @@ __global__ __launch_bounds__(128) void coeff_kernel(const InstDev *__restrict__ 
             tau_next = tn1;
 #pragma unroll
             for (int j = 0; j < ND; ++j) {
-                Fge q = fge_stage_t<RULE>(mu, I.om[j], tn1, dt * sch->a[0], substeps);
-                status = status ? status : q.status;
-                r.chi[j] = fprev[j] + q.e;
+                double e_next;
+                if (have_next) {
+                    e_next = first_e[j][threadIdx.x + 1];
+                } else {
+                    Fge q = fge_stage_t<RULE>(mu, I.om[j], tn1, dt * sch->a[0], substeps);
+                    status = status ? status : q.status;
+                    e_next = q.e;
+                }
+                r.chi[j] = fprev[j] + e_next;
             }
             r.w = dt * (sch->b[m] + sch->b[0]);
         } else {
@@ -257,7 +277,7 @@ hipError_t launch_coeff(const LaunchCoeff &L)
 {
     int64_t total = (int64_t)L.n_inst * L.k_steps;
     if (total <= 0) return hipSuccess;
-    const int bs = 128;
+    const int bs = kCoeffThreads;
     int64_t grid = (total + bs - 1) / bs;
     if (L.recx) {
         hipLaunchKernelGGL(coeff_coupled_kernel, dim3((unsigned)grid), dim3(bs), 0, L.stream, L.insts, L.n_inst,

@@ -29,7 +29,7 @@ struct Ksum {
 template <typename Store>
 __global__ __launch_bounds__(256) void reduce_kernel(const InstDev *__restrict__ insts, int nblk,
                                                      const Store *__restrict__ psi, int energy,
-                                                     double t, const double *__restrict__ vi,
+                                                     double t, const void *__restrict__ vi, int vi_f32,
                                                      double *__restrict__ part)
 {
     __shared__ double sh[3][256];
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const InstDev *__restrict__
             }
             if (I.coupled)  // off-diagonal part of (mu/2) x^T W x
                 V += I.mu * (wx[0] * xs[0] * xs[1] + wx[1] * xs[0] * xs[2] + wx[2] * xs[1] * xs[2]);
-            V += vm * (vi ? vi[I.offset + idx] : I.eps * VI);
+            V += vm * (vi ? vi_at(vi, vi_f32, I.offset + idx) : I.eps * VI);
             b.add(V * a2);
             c.add(0.5 * sig * a2 * a2);
         }
@@ -87,10 +87,10 @@ hipError_t launch_reduce_pointwise(const LaunchReduce &L)
     dim3 grid((unsigned)(L.n_inst * L.nblk));
     if (L.c64)
         hipLaunchKernelGGL(reduce_kernel<float2>, grid, dim3(256), 0, L.stream, L.insts, L.nblk,
-                           (const float2 *)L.psi, L.energy, L.t, L.vi, L.part);
+                           (const float2 *)L.psi, L.energy, L.t, L.vi, L.vi_f32, L.part);
     else
         hipLaunchKernelGGL(reduce_kernel<double2>, grid, dim3(256), 0, L.stream, L.insts, L.nblk,
-                           (const double2 *)L.psi, L.energy, L.t, L.vi, L.part);
+                           (const double2 *)L.psi, L.energy, L.t, L.vi, L.vi_f32, L.part);
     return hipGetLastError();
 }
 

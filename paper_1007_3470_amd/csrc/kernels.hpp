@@ -38,7 +38,8 @@ struct Launch1D {
     const Rec *rec;
     const Rec *rec_open;
     const double2 *cistab;  // the phase table (CisTable layout), 16-byte words
-    const double *vi;       // caller's eps V_I per point (state layout), or null
+    const void *vi;         // caller's eps V_I per point (state layout), or null
+    int vi_f32;             // 1: vi holds floats, 0: doubles
     void *psi;
     int m;
     int K;            // steps advanced by this launch
@@ -63,7 +64,8 @@ struct LaunchReduce {
     int c64;
     int energy;        // 0: only |u|^2
     double t;          // time for omega(t), sigma(t)
-    const double *vi;  // caller's eps V_I per point, or null (factor form)
+    const void *vi;    // caller's eps V_I per point, or null (factor form)
+    int vi_f32;        // 1: vi holds floats, 0: doubles
     double *part;
     hipStream_t stream;
 };
@@ -94,7 +96,8 @@ struct LaunchND {
     const RecX *recx;       // coupled trap: off-diagonal G and chirp entries, else null
     const RecX *recx_open;
     int kind;               // 0 separable stage pass, 1 forward only, 2 forward + whole drift + inverse, 3 inverse only
-    const double *vi;       // caller's eps V_I per point (state layout), or null
+    const void *vi;         // caller's eps V_I per point (state layout), or null
+    int vi_f32;             // 1: vi holds floats, 0: doubles
     const double *vtab;  // [n_inst][3][vtab_stride]: V_I factor of each axis on its grid
     int vtab_stride;
     const double2 *cistab;

@@ -83,6 +83,12 @@ struct Item1D {
     int pad_;
 };
 
+// eps V_I at element k of a caller's array held in FP64 (f32 = 0) or FP32.
+__host__ __device__ inline double vi_at(const void *vi, int f32, int64_t k)
+{
+    return f32 ? (double)static_cast<const float *>(vi)[k] : static_cast<const double *>(vi)[k];
+}
+
 __host__ __device__ inline double vfactor(const VFac &v, double x)
 {
     double x2 = x * x;

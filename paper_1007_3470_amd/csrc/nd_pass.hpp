@@ -87,7 +87,7 @@ template <typename Store, int P, int MAXS, int MODE, int TPB, int KIND, int FIX>
 __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
     const InstDev *__restrict__ insts, int n_inst, const Rec *__restrict__ rec,
     const Rec *__restrict__ rec_open, const RecX *__restrict__ recx, const RecX *__restrict__ recx_open,
-    const double *__restrict__ vi, const double *__restrict__ vtab, int vtab_stride,
+    const void *__restrict__ vi, int vi_f32, const double *__restrict__ vtab, int vtab_stride,
     const double2 *__restrict__ cistab, const double2 *__restrict__ twtab, int twlog,
     Store *__restrict__ psi, NdShape sh, int axis, int lG, int stage, int m, int rec_steps, int step_off,
     const int *__restrict__ step_base)
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(TPB, (TPB <= 256 ? 2 : 1)) void hfnd_pass_kernel(
                     // eps V_I: the caller's value at the point, or the factor form
                     const double rest = fma(q.s, a2, pen.th0);
                     const double bv =
-                        vi ? fma(q.w, vi[I.offset + base + i * estr], rest) : fma(pen.wv0, xv.y, rest);
+                        vi ? fma(q.w, vi_at(vi, vi_f32, I.offset + base + i * estr), rest) : fma(pen.wv0, xv.y, rest);
                     th[cc] = fma(xv.x, fma(chia, 0.5 * xv.x, pen.lin), bv);
                 }
                 cis_apply_batch<XB>(u + c0, th, ctab);
@@ -431,7 +431,7 @@ hipError_t launch_pass_tpb(const LaunchND &L)
         grid = (int)(groups < want ? (groups > 0 ? groups : 1) : want);
     }
     hipLaunchKernelGGL((hfnd_pass_kernel<Store, P, MAXS, MODE, TPB, KIND, FIX>), dim3(grid), dim3(threads), 0,
-                       L.stream, L.insts, L.n_inst, L.rec, L.rec_open, L.recx, L.recx_open, L.vi, L.vtab,
+                       L.stream, L.insts, L.n_inst, L.rec, L.rec_open, L.recx, L.recx_open, L.vi, L.vi_f32, L.vtab,
                        L.vtab_stride, L.cistab, L.twtab, L.twlog, (Store *)L.psi, sh, L.axis, lG, L.stage, L.m,
                        L.rec_steps, L.step, L.step_base);
     return hipGetLastError();

@@ -37,9 +37,12 @@ def test_buffer_checks(pkg):
     with pytest.raises(ValueError):
         plan.pack([np.zeros(17, complex)])
     with pytest.raises(TypeError):
-        plan.set_potential(torch.zeros(256, dtype=torch.float32, device="cuda"))
+        plan.set_potential(torch.zeros(256, dtype=torch.float16, device="cuda"))
     with pytest.raises(ValueError):
         plan.set_potential(torch.zeros(255, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.set_potential(torch.zeros(255, dtype=torch.float32, device="cuda"))
+    plan.set_potential(None)
     plan.evolve(good, 0.0, 2)
     torch.cuda.synchronize()
     assert plan.device_status() == 0

@@ -1,6 +1,7 @@
 """GPU parity with a caller-supplied perturbation: eps V_I given as a device
-array at every grid point (hfgpe_set_potential), against the oracle given the
-same values."""
+array at every grid point, in FP64 (hfgpe_set_potential) or FP32
+(hfgpe_set_potential_f32), against the oracle given the same values (for
+FP32, the rounded values written out in FP64)."""
 from dataclasses import replace
 
 import numpy as np
@@ -110,4 +111,52 @@ def test_potential_energy_and_reset(pkg):
     ref_plan.evolve(b3, w.t0, w.nsteps)
     torch.cuda.synchronize()
     for a, b in zip(plan.unpack(b2), ref_plan.unpack(b3)):
+        assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# the FP32 form: the oracle takes the same (rounded) values in FP64
+# ---------------------------------------------------------------------------
+def run_f32(pkg, w, dtype, vis, **kw):
+    import torch
+    plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, **kw)
+    plan.set_potential(plan.pack_real(vis).to(torch.float32))
+    buf = plan.pack(w.psi0)
+    plan.evolve(buf, w.t0, w.nsteps)
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    return plan, buf, plan.unpack(buf)
+
+
+def rounded(vis):
+    return [np.asarray(v, dtype=np.float32).astype(np.float64) for v in vis]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_potential_f32_1d_2d_3d(pkg, dtype):
+    base = W.batch_1d(n_inst=6, sizes=(32, 256, 1024, 4096), nsteps=20, seed=16)
+    for w, kw in ((base, {}), (W.gpe_2d(n=64, n_inst=2, nsteps=12), {"use_graph": True}),
+                  (W.gpe_3d(n=32, nsteps=3), {})):
+        vis = rounded([potential(i, k) for k, i in enumerate(w.instances)])
+        _, _, got = run_f32(pkg, w, dtype, vis, **kw)
+        check(w, got, vis, TOL[dtype])
+
+
+def test_potential_f32_energy_and_switch(pkg):
+    """Energy with the FP32 array; switching to the FP64 array of the same
+    values gives the same bits (the same doubles enter the phase)."""
+    import torch
+    w = W.coupled_2d(n=64, n_inst=2, nsteps=8)
+    vis = rounded([potential(i, k) for k, i in enumerate(w.instances)])
+    plan, buf, got = run_f32(pkg, w, "c128", vis)
+    check(w, got, vis, 1e-11)
+    t = w.t0 + w.nsteps * w.dt
+    en = plan.energy(buf, t)
+    for k, inst in enumerate(w.instances):
+        assert np.allclose(en[k], oracle.energy(inst, got[k], t, vi=vis[k]), rtol=1e-11, atol=1e-11)
+    plan.set_potential(plan.pack_real(vis))
+    b2 = plan.pack(w.psi0)
+    plan.evolve(b2, w.t0, w.nsteps)
+    torch.cuda.synchronize()
+    for a, b in zip(plan.unpack(b2), got):
         assert np.array_equal(a, b)
