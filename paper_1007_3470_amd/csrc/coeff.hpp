@@ -89,11 +89,15 @@ __host__ __device__ inline Fge fge_cf4(double mu, const Om &om, double t0, doubl
     if (!(qL > 0.0) || !(qR > 0.0)) { r.status = -4; return r; }
     double wL = sqrt(qL), wR = sqrt(qR);
     double yL = 0.5 * wL * tau, yR = 0.5 * wR * tau;
-    double cL = cos(yL), sL = sin(yL), cR = cos(yR), sR = sin(yR);
+    double cL, sL, cR, sR;
+    sincos(yL, &sL, &cL);
+    sincos(yR, &sR, &cR);
     double g = sL * cR / wL + cL * sR / wR;
     if (!(g * tau > 0.0)) { r.status = -3; return r; }
-    // 1 - cL cR = (1 - cL) + cL (1 - cR)
-    double one_m = versin(yL) + cL * versin(yR);
+    // 1 - cL cR = (1 - cL) + cL (1 - cR), with 1 - cos y = sin^2 y / (1 + cos y):
+    // no cancellation while 1 + cos y stays away from 0, which holds for the
+    // half-stage angles |y| < pi/2 of every stage the plan's validation accepts
+    double one_m = sL * sL / (1.0 + cL) + cL * (sR * sR / (1.0 + cR));
     r.g = g / mu;
     r.f = mu * (one_m + wL / wR * sL * sR) / g;
     r.e = mu * (one_m + wR / wL * sL * sR) / g;

@@ -17,7 +17,6 @@
 // exchange type (FP64 for both).  Arithmetic is FP64 throughout.
 #include <hip/hip_runtime.h>
 
-#include "coeff.hpp"
 #include "devmath.hpp"
 #include "fft_lds.hpp"
 #include "kernels.hpp"

@@ -29,7 +29,6 @@
 
 #include <atomic>
 
-#include "coeff.hpp"
 #include "devmath.hpp"
 #include "fft_lds.hpp"
 #include "kernels.hpp"
