@@ -37,7 +37,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_hf1d_batch1d.json")
 # Sources of a measured kernel's translation unit (the .hip file and every
 # header it includes): a change to any of them makes stored counters stale;
 # host-only changes (the API runtime) do not.
-KERNEL_TU_1D = ("kern_1d.hip", "devmath.hpp", "fft_lds.hpp", "kernels.hpp", "layout.hpp")
+KERNEL_TU_1D = ("kern_1d.hip", "hf1d_fixed.hpp", "coeff_step.hpp", "coeff.hpp", "devmath.hpp",
+                "fft_lds.hpp", "kernels.hpp", "layout.hpp")
 KERNEL_TU_ND = ("nd_pass.hpp", "kern_nd.hip", "kern_nd_fix.hip", "kern_nd_fix_coupled.hip",
                 "devmath.hpp", "fft_lds.hpp", "kernels.hpp", "layout.hpp")
 

@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 #define HFGPE_VERSION_MAJOR 0
-#define HFGPE_VERSION_MINOR 2
+#define HFGPE_VERSION_MINOR 3
 
 /* Status codes. */
 #define HFGPE_OK 0
@@ -204,6 +204,17 @@ typedef struct {
                               The merged phases carry across chunk boundaries,
                               so results do not depend on it (bitwise for
                               FP64).  Negative: INVALID_ARG */
+    int in_kernel_records; /* 1-D: 1 = a plan whose grid sizes all lie in
+                              64..2048 evaluates the stage coefficients inside
+                              the resident step kernel, per block of steps, with
+                              the coefficient kernel's arithmetic (the same bits
+                              in FP64): no record table traffic and no chunks,
+                              but each workgroup waits for its records, so it is
+                              slower on batches of many workgroups; 0 (default)
+                              = a coefficient kernel writes a record table
+                              before each chunk (always so for d-D plans, host
+                              callbacks and the plain schedule).  Other values:
+                              INVALID_ARG */
 } hfgpe_options;
 
 typedef struct hfgpe_plan hfgpe_plan;

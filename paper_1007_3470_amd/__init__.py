@@ -83,7 +83,7 @@ class Options(ctypes.Structure):
     _fields_ = [("steps_per_launch", ctypes.c_int), ("plain", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("profile", ctypes.c_int),
                 ("nd_workgroups", ctypes.c_int), ("nd_generic", ctypes.c_int),
-                ("chunk_steps", ctypes.c_int)]
+                ("chunk_steps", ctypes.c_int), ("in_kernel_records", ctypes.c_int)]
 
 
 # int fn(void *user, int inst, int axis, double t0, double tau, double mu, double *fge)
@@ -235,7 +235,8 @@ class Plan:
     def __init__(self, instances: Sequence, scheme: str = "leapfrog", ho_rule: str = "cf4",
                  dtype: str = "c128", dt: float = 1e-3, steps_per_launch: int = 0,
                  plain: bool = False, use_graph: bool = False, profile: int = 0,
-                 nd_workgroups: int = 0, nd_generic: bool = False, chunk_steps: int = 0, stream=None,
+                 nd_workgroups: int = 0, nd_generic: bool = False, chunk_steps: int = 0,
+                 in_kernel_records: bool = False, stream=None,
                  a: Optional[Sequence[float]] = None, b: Optional[Sequence[float]] = None):
         import torch
         self.lib = load()
@@ -250,7 +251,8 @@ class Plan:
         grids = (Grid * max(1, self.n_inst))(*[make_grid(i) for i in instances])
         params = (Params * max(1, self.n_inst))(*[make_params(i) for i in instances])
         opts = Options(int(steps_per_launch), int(bool(plain)), int(bool(use_graph)),
-                       int(profile), int(nd_workgroups), int(bool(nd_generic)), int(chunk_steps))
+                       int(profile), int(nd_workgroups), int(bool(nd_generic)), int(chunk_steps),
+                       int(bool(in_kernel_records)))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -115,6 +115,46 @@ __device__ __forceinline__ void cis_apply_batch(double2 *u, const double *theta,
     }
 }
 
+// f[c] = exp(-i theta[c]) for c < NP: the factors of cis_apply_batch (same
+// arithmetic, table reads issued together) without the multiply.
+template <int NP>
+__device__ __forceinline__ void cis_batch(const double *theta, double2 *f, const CisTable &tab)
+{
+    const double K = 40.743665431525208;
+    const double C_HI = 0.024543692606170259;
+    const double C_LO = 9.5714723039735938e-19;
+    double r[NP];
+    int j[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+        const double n = rint(theta[c] * K);
+        double rr = fma(-n, C_HI, theta[c]);
+        r[c] = fma(-n, C_LO, rr);
+        j[c] = ((int)n) & (kCisTable - 1);
+    }
+    double2 t[NP];
+    float2 cor[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+        t[c] = tab.t[j[c]];
+        cor[c] = tab.c[j[c]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+        const double rho = r[c] - (double)cor[c].x;
+        const double r2 = rho * rho;
+        double ps = fma(r2, -1.984126984126984e-04, 8.333333333333333e-03);
+        ps = fma(ps, r2, -1.6666666666666666e-01);
+        const double sn = fma(rho * r2, ps, rho);
+        double pc = fma(r2, -1.3888888888888889e-03, 4.1666666666666664e-02);
+        pc = fma(pc, r2, -0.5);
+        const double cm = fma(r2, pc, (double)cor[c].y);
+        const double tx = t[c].x, ty = t[c].y;
+        f[c] = make_double2(fma(tx, cm, fma(ty, sn, tx)), fma(ty, cm, fma(-tx, sn, ty)));
+    }
+}
+
 // copy the table (as raw 16-byte words) from global memory into LDS
 __device__ __forceinline__ void load_cis_table(CisTable *lds_tab, const double2 *__restrict__ gtab)
 {

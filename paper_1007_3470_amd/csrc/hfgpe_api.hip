@@ -961,6 +961,7 @@ int hfgpe_plan_create(hfgpe_plan **out, int n_inst, const hfgpe_grid *grids, con
     if (n_inst < 0 || (n_inst > 0 && (!grids || !params))) return HFGPE_E_INVALID_ARG;
     if (dtype != HFGPE_C64 && dtype != HFGPE_C128) return HFGPE_E_INVALID_ARG;
     if (opts && opts->chunk_steps < 0) return HFGPE_E_INVALID_ARG;
+    if (opts && (opts->in_kernel_records < 0 || opts->in_kernel_records > 1)) return HFGPE_E_INVALID_ARG;
     if (!std::isfinite(dt) || dt == 0.0) return HFGPE_E_INVALID_ARG;
     int nd = (n_inst > 0) ? grids[0].ndim : 1;
     if (nd < 1 || nd > 3) return HFGPE_E_INVALID_ARG;
@@ -1213,6 +1214,20 @@ int hfgpe_instance_offsets(const hfgpe_plan *plan, int64_t *off)
     return HFGPE_OK;
 }
 
+// steps per launch sequence when the records are evaluated in the kernel
+constexpr int kFusedChunkMax = 1 << 30;
+
+// In-kernel stage records: asked for, on a 1-D plan without host callbacks,
+// not on the plain schedule, whose every group runs the fixed-shape kernel.
+static bool fused_records_1d(const hfgpe_plan &P)
+{
+    if (!P.opts.in_kernel_records || P.ndim != 1 || P.stage_fn || P.coef_fn || P.opts.plain) return false;
+    if (P.groups.empty()) return false;
+    for (const auto &g : P.groups)
+        if (!g.fixed) return false;
+    return true;
+}
+
 int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
 {
     if (!P || nsteps < 0 || !std::isfinite(t0)) return HFGPE_E_INVALID_ARG;
@@ -1220,8 +1235,13 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
     if (!d_psi || !state_aligned(P, d_psi)) return HFGPE_E_INVALID_ARG;
     const int m = P->scheme.m;
     const bool host_records = P->stage_fn || P->coef_fn;
-    int chunk = (int)std::min<int64_t>(nsteps, host_records ? P->cb_steps_cap : P->rec_steps_cap);
     const bool plain = P->opts.plain != 0;
+    // on request, 1-D plans whose groups all take the fixed-shape kernel
+    // evaluate the stage records inside the step kernel: no coefficient
+    // kernel, no record table traffic, no chunking
+    const bool fused = fused_records_1d(*P);
+    int chunk = (int)std::min<int64_t>(nsteps, fused ? kFusedChunkMax
+                                                     : (host_records ? P->cb_steps_cap : P->rec_steps_cap));
     int per_launch = plain ? 1 : (P->opts.steps_per_launch > 0 ? P->opts.steps_per_launch : chunk);
     for (int64_t s0 = 0; s0 < nsteps; s0 += chunk) {
         int k = (int)std::min<int64_t>(chunk, nsteps - s0);
@@ -1255,7 +1275,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
                                        hipMemcpyHostToDevice, P->stream));
             HIP_TRY(hipEventRecord(P->stage_ev, P->stream));
             P->stage_ev_pending = true;
-        } else {
+        } else if (!fused) {
             // the coefficient kernel is bracketed only at profile level 2: two
             // event records between it and the step kernel widen the gap
             // between the two
@@ -1313,6 +1333,13 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
                 L.step_base = sb;
                 L.apply_opening = (s0 == 0 && sb == 0) ? 1 : 0;
                 L.c64 = P->dtype == HFGPE_C64;
+                L.coef_rule = fused ? P->scheme.rule : -1;
+                L.scheme = P->d_scheme;
+                L.t0 = t0;
+                L.dt = P->dt;
+                L.step0 = s0;
+                L.nsteps_total = nsteps;
+                L.err = P->d_err;
                 L.stream = P->stream;
                 std::pair<hipEvent_t, hipEvent_t> es{};
                 if (P->opts.profile) {

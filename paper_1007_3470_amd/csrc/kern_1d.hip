@@ -19,6 +19,7 @@
 
 #include "devmath.hpp"
 #include "fft_lds.hpp"
+#include "hf1d_fixed.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 
@@ -107,111 +108,6 @@ __global__ __launch_bounds__(kThreads1D, (P <= 8 ? 2 : 1)) void hf1d_kernel(cons
     if (active) {
 #pragma unroll
         for (int c = 0; c < P; ++c) base[tl + c * T] = from_d2<Store>(u[c]);
-    }
-}
-
-// The same resident step for 64 <= N <= 2048 (8 points per thread) with the
-// FFT shape fixed at compile time (FftFix8): one body per grid size, selected
-// per workgroup, so LDS addresses and index arithmetic are constants.
-template <typename Store, int LOGN>
-__device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__restrict__ perm,
-                                                const InstDev *__restrict__ insts, const Rec *__restrict__ rec,
-                                                const Rec *__restrict__ rec_open, const CisTable &ctab,
-                                                const void *__restrict__ vi, int vi_f32, double2 *lds, double *vel,
-                                                Store *__restrict__ psi, int m,
-                                                int K, int rec_steps, int step_base, int apply_opening)
-{
-    using F = FftFix8<LOGN>;
-    constexpr int P = 8, N = F::N, T = F::T;
-    const int tid = threadIdx.x;
-    const int slot = tid >> F::LOGT;
-    const int tl = tid & (T - 1);
-    const bool active = slot < it.count;
-    const int inst_id = perm[it.first + (active ? slot : 0)];
-    const InstDev &I = insts[inst_id];
-
-    F fft;
-    fft.init(tl, slot, lds);
-
-    double2 u[P];
-    const double lo = I.lo[0], dx = I.dx[0], eps = I.eps;
-    const VFac vf = I.vf[0];
-    Store *base = psi + I.offset;
-    double *ve = vel + slot * N + tl;
-#pragma unroll
-    for (int c = 0; c < P; ++c) {
-        const int i = tl + c * T;
-        const double x = lo + (double)i * dx;
-        ve[c * T] = vi ? vi_at(vi, vi_f32, I.offset + i) : eps * vfactor(vf, x);
-        u[c] = active ? to_d2(base[i]) : make_double2(0.0, 0.0);
-    }
-    __syncthreads();  // cis table in LDS
-
-    auto xphase = [&](const Rec &r) {
-        const double chi = r.chi[0], w = r.w, s = r.s;
-        double th[P];
-#pragma unroll
-        for (int c = 0; c < P; ++c) {
-            const double x = lo + (double)(tl + c * T) * dx;
-            const double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
-            th[c] = fma(chi, 0.5 * x * x, fma(w, ve[c * T], s * a2));
-        }
-        cis_apply_batch<P>(u, th, ctab);
-    };
-
-    constexpr double invN = 1.0 / (double)N;
-    const double ks = I.kscale[0];
-    if (apply_opening) xphase(rec_open[inst_id]);
-    const Rec *rp = rec + ((size_t)inst_id * (size_t)rec_steps + (size_t)step_base) * (size_t)m;
-    for (int step = 0; step < K; ++step) {
-        for (int st = 0; st < m; ++st) {
-            const Rec r = rp[step * m + st];
-            fft.template run<-1>(u);
-            const double g = r.g[0];
-            double th[P];
-#pragma unroll
-            for (int c = 0; c < P; ++c) {
-                // wavenumber index: the upper half of the points is negative
-                const int sq = tl + c * T - ((c >= P / 2) ? N : 0);
-                const double k = ks * (double)sq;
-                th[c] = g * (0.5 * k * k);
-            }
-            cis_apply_batch<P>(u, th, ctab, invN);
-            fft.template run<+1>(u);
-            xphase(r);
-        }
-    }
-    if (active) {
-#pragma unroll
-        for (int c = 0; c < P; ++c) base[tl + c * T] = from_d2<Store>(u[c]);
-    }
-}
-
-template <typename Store>
-__global__ __launch_bounds__(kThreads1D, 2) void hf1d_fixed_kernel(const Item1D *__restrict__ items,
-                                                                const int *__restrict__ perm,
-                                                                const InstDev *__restrict__ insts,
-                                                                const Rec *__restrict__ rec,
-                                                                const Rec *__restrict__ rec_open,
-                                                                const double2 *__restrict__ cistab,
-                                                                const void *__restrict__ vi, int vi_f32,
-                                                                Store *__restrict__ psi, int m, int K,
-                                                                int rec_steps, int step_base, int apply_opening)
-{
-    constexpr int LDS_ELEMS = kThreads1D * 8 + ((kThreads1D * 8) >> kPadShift);
-    __shared__ double2 lds[LDS_ELEMS];
-    __shared__ CisTable ctab;
-    __shared__ double vel[kThreads1D * 8];
-    load_cis_table(&ctab, cistab);
-    const Item1D it = items[blockIdx.x];
-    switch (it.logn) {
-    case 6: hf1d_fixed_body<Store, 6>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 7: hf1d_fixed_body<Store, 7>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 8: hf1d_fixed_body<Store, 8>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 9: hf1d_fixed_body<Store, 9>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 10: hf1d_fixed_body<Store, 10>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    case 11: hf1d_fixed_body<Store, 11>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, psi, m, K, rec_steps, step_base, apply_opening); break;
-    default: break;  // the launcher sends only 64 <= N <= 2048 here
     }
 }
 
@@ -317,11 +213,10 @@ static hipError_t launch_store(const Launch1D &L)
 {
     if (L.fixed) {
         if (L.P != 8) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((hf1d_fixed_kernel<Store>), dim3(L.n_items), dim3(kThreads1D), 0, L.stream, L.items,
-                           L.perm, L.insts, L.rec, L.rec_open, L.cistab, L.vi, L.vi_f32, (Store *)L.psi, L.m, L.K,
-                           L.rec_steps, L.step_base, L.apply_opening);
-        return hipGetLastError();
+        if (L.coef_rule >= 0) return launch_hf1d_fused(L);  // kern_1d_fused.hip
+        return launch_hf1d_fixed<Store, -1>(L);
     }
+    if (L.coef_rule >= 0) return hipErrorInvalidValue;  // in-kernel records: fixed shapes only
     switch (L.P) {
     case 1: return launch_p<Store, Xch, 1, 1>(L);
     case 2: return launch_p<Store, Xch, 2, 1>(L);

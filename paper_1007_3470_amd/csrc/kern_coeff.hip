@@ -1,30 +1,13 @@
-// kern_coeff.hip -- per (instance, step) stage-coefficient kernel.
-//
-// For every instance and every step n of a chunk it evaluates, in FP64, the
-// harmonic-oscillator coefficients (f, g, e) of each stage i over
-// [tau_i, tau_i + a_i dt] with tau_i = t_n + dt (a_0 + ... + a_{i-1}) (time
-// frozen in B as in Table "algorithm"), and writes one record per stage: the
-// stage's drift coefficient g_i and the x-space phase applied after it, in
-// which adjacent chirps and B flows are merged (Eq. leapfrogHF,
-// Eq. prod-genHarmOsc):
-//   inside a step:         chi = f_i + e_{i+1},      w = dt b_{i+1} at tau_{i+1}
-//   across a step boundary: chi = f_{m-1} + e'_0,     w = dt (b_m + b_0) at t_{n+1}
-//   after the last step:    chi = f_{m-1},            w = dt b_m at t_{n+1}
-// and s = w sigma(tau).  Under the Fourier split (no chirps) chi is instead
-// w mu omega_j(tau)^2, the harmonic potential of the B flow.  The opening phase of an evolve call
-// (chi = e_0(t_0), w = dt b_0 at t_0) goes to rec_open.
+// kern_coeff.hip -- per (instance, step) stage-coefficient kernels: the
+// merged records of every step of a chunk (coeff_step.hpp; separable traps)
+// written to the plan's record table, and the coupled-trap records.
 #include <hip/hip_runtime.h>
 
-#include "coeff.hpp"
+#include "coeff_step.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 
 namespace hfgpe {
-
-__device__ __forceinline__ void raise_err(int *err, int code)
-{
-    if (code != 0) atomicCAS(err, 0, code);
-}
 
 // One instantiation per (HO rule, dimension): the stage loop over axes
 // unrolls and the per-axis coefficients stay in registers.  Consecutive
@@ -47,96 +30,22 @@ __global__ __launch_bounds__(kCoeffThreads) void coeff_kernel(const InstDev *__r
     const bool active = idx < total;
     const int inst = active ? (int)(idx / k_steps) : 0;
     const int s = active ? (int)(idx % k_steps) : 0;
-    const InstDev &I = insts[inst];
-    const int m = sch->m, substeps = sch->substeps;
-    const double mu = I.mu;
     const int64_t n = step0 + s;
-    const double tn = t0 + (double)n * dt;
-    const double tn1 = t0 + (double)(n + 1) * dt;
-    const bool last = (n == nsteps_total - 1);
-    int status = 0;
-
-    Rec *out = rec + ((size_t)inst * k_steps + s) * m;
-    Fge cur[ND];
+    StepCoeffs<RULE, ND> sc(insts[inst], *sch, t0, dt, n, nsteps_total);
+    if (active) sc.first();
 #pragma unroll
-    for (int j = 0; j < ND; ++j) {
-        cur[j] = active ? fge_stage_t<RULE>(mu, I.om[j], tn, dt * sch->a[0], substeps) : Fge{0.0, 0.0, 0.0, 0};
-        status = status ? status : cur[j].status;
-        first_e[j][threadIdx.x] = cur[j].e;
-    }
+    for (int j = 0; j < ND; ++j) first_e[j][threadIdx.x] = active ? sc.cur[j].e : 0.0;
     __syncthreads();
     // the neighbour holds step n + 1 of the same instance
     const bool have_next = threadIdx.x + 1 < blockDim.x && idx + 1 < total && s + 1 < k_steps;
     if (!active) return;
-    if (n == 0) {
-        Rec o;
+    if (n == 0) rec_open[inst] = sc.opening();
+    double e_next[ND];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) { o.g[j] = 0.0; o.chi[j] = 0.0; }
-#pragma unroll
-        for (int j = 0; j < ND; ++j) o.chi[j] = cur[j].e;
-        o.w = dt * sch->b[0];
-        o.s = o.w * tf_value(I.sig, tn);
-        if constexpr (RULE == 3) {
-#pragma unroll
-            for (int j = 0; j < ND; ++j) o.chi[j] += o.w * mu * tf_square(I.om[j], tn);
-        }
-        o.w *= tf_value(I.vmod, tn);  // eps V_I(x, t) = m(t) eps V_I(x)
-        rec_open[inst] = o;
-    }
-    for (int i = 0; i < m; ++i) {
-        Rec r;
-        double fprev[ND];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) { r.g[j] = 0.0; r.chi[j] = 0.0; }
-#pragma unroll
-        for (int j = 0; j < ND; ++j) {
-            r.g[j] = cur[j].g;
-            fprev[j] = cur[j].f;
-        }
-        double tau_next;
-        if (i < m - 1) {
-            tau_next = tn + dt * sch->cum[i + 1];
-#pragma unroll
-            for (int j = 0; j < ND; ++j) {
-                cur[j] = fge_stage_t<RULE>(mu, I.om[j], tau_next, dt * sch->a[i + 1], substeps);
-                status = status ? status : cur[j].status;
-                r.chi[j] = fprev[j] + cur[j].e;
-            }
-            r.w = dt * sch->b[i + 1];
-        } else if (!last) {
-            tau_next = tn1;
-#pragma unroll
-            for (int j = 0; j < ND; ++j) {
-                double e_next;
-                if (have_next) {
-                    e_next = first_e[j][threadIdx.x + 1];
-                } else {
-                    Fge q = fge_stage_t<RULE>(mu, I.om[j], tn1, dt * sch->a[0], substeps);
-                    status = status ? status : q.status;
-                    e_next = q.e;
-                }
-                r.chi[j] = fprev[j] + e_next;
-            }
-            r.w = dt * (sch->b[m] + sch->b[0]);
-        } else {
-            tau_next = tn1;
-#pragma unroll
-            for (int j = 0; j < ND; ++j) r.chi[j] = fprev[j];
-            r.w = dt * sch->b[m];
-        }
-        r.s = r.w * tf_value(I.sig, tau_next);
-        if constexpr (RULE == 3) {  // Fourier split: the harmonic potential is part of B
-#pragma unroll
-            for (int j = 0; j < ND; ++j) r.chi[j] += r.w * mu * tf_square(I.om[j], tau_next);
-        }
-        r.w *= tf_value(I.vmod, tau_next);
-        bool finite = isfinite(r.w) && isfinite(r.s);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) finite = finite && isfinite(r.g[j]) && isfinite(r.chi[j]);
-        if (!finite && !status) status = -7;
-        out[i] = r;
-    }
-    raise_err(err, status);
+    for (int j = 0; j < ND; ++j) e_next[j] = have_next ? first_e[j][threadIdx.x + 1] : 0.0;
+    Rec *out = rec + ((size_t)inst * k_steps + s) * sch->m;
+    sc.records(have_next ? e_next : nullptr, [&](int i, const Rec &r) { out[i] = r; });
+    raise_err(err, sc.status);
 }
 
 // Coupled trap (non-diagonal W, d >= 2): one record per effective stage (two

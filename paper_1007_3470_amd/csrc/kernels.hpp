@@ -47,9 +47,18 @@ struct Launch1D {
     int step_base;    // first step of this launch within rec
     int apply_opening;
     int c64;
+    // in-kernel stage records (fixed shapes): coef_rule = the HO rule; -1 =
+    // records from rec / rec_open
+    int coef_rule;
+    const SchemeDev *scheme;  // device copy
+    double t0, dt;
+    int64_t step0;            // global index of the chunk's first step
+    int64_t nsteps_total;     // steps of the evolve call
+    int *err;                 // device error word
     hipStream_t stream;
 };
 hipError_t launch_hf1d(const Launch1D &L);
+hipError_t launch_hf1d_fused(const Launch1D &L);  // coef_rule >= 0, fixed shapes
 int points_per_thread_1d(int n);
 bool fixed_shape_1d(int n);
 

@@ -51,7 +51,7 @@ def test_version_and_status_strings():
     lib = pkg.load()
     ma, mi = ctypes.c_int(), ctypes.c_int()
     assert lib.hfgpe_version(ctypes.byref(ma), ctypes.byref(mi)) == 0
-    assert (ma.value, mi.value) == (0, 2)
+    assert (ma.value, mi.value) == (0, 3)
     for code in range(-8, 1):
         assert lib.hfgpe_status_string(code).decode() != "unknown status"
     assert lib.hfgpe_status_string(-99).decode() == "unknown status"
@@ -146,7 +146,7 @@ def test_exact_const_matches_oracle_for_constant_squared_form():
                                      mu * w * math.tan(w * t / 2)], rtol=1e-14, atol=0)
 
 
-def _create(instances, scheme="leapfrog", rule="cf4", dtype=1, dt=1e-3, m=None, a=None, b=None):
+def _create(instances, scheme="leapfrog", rule="cf4", dtype=1, dt=1e-3, m=None, a=None, b=None, opts=None):
     lib = pkg.load()
     if a is None:
         a, b = pkg.scheme_preset(scheme)
@@ -156,7 +156,8 @@ def _create(instances, scheme="leapfrog", rule="cf4", dtype=1, dt=1e-3, m=None, 
     g = (pkg.Grid * max(1, n))(*[pkg.make_grid(i) for i in instances])
     p = (pkg.Params * max(1, n))(*[pkg.make_params(i) for i in instances])
     h = ctypes.c_void_p()
-    rc = lib.hfgpe_plan_create(ctypes.byref(h), n, g, p, ctypes.byref(sch), dtype, dt, None, None)
+    rc = lib.hfgpe_plan_create(ctypes.byref(h), n, g, p, ctypes.byref(sch), dtype, dt,
+                               None if opts is None else ctypes.byref(opts), None)
     if rc == 0:
         lib.hfgpe_plan_destroy(h)
     return rc
@@ -170,6 +171,11 @@ def _gpu_or_nodevice(rc):
 def test_plan_validation_codes():
     base = W.gpe_1d(n=64, nsteps=0).instances[0]
     assert _gpu_or_nodevice(_create([base]))
+    # options: chunk_steps >= 0, in_kernel_records 0 or 1
+    assert _gpu_or_nodevice(_create([base], opts=pkg.Options(in_kernel_records=1)))
+    assert _create([base], opts=pkg.Options(in_kernel_records=2)) == -1
+    assert _create([base], opts=pkg.Options(in_kernel_records=-1)) == -1
+    assert _create([base], opts=pkg.Options(chunk_steps=-1)) == -1
     assert _create([replace(base, n=(48, 1, 1))]) == -2              # not a power of two
     assert _create([replace(base, n=(8192, 1, 1))]) == -2            # beyond the 1-D limit
     assert _create([replace(base, n=(64, 2, 1))]) == -2              # unused axis not 1
