@@ -65,7 +65,7 @@ template <typename Store, int LOGN, int RULE>
 __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__restrict__ perm,
                                                 const InstDev *__restrict__ insts, const Rec *__restrict__ rec,
                                                 const Rec *__restrict__ rec_open, const CisTable &ctab,
-                                                const void *__restrict__ vi, int vi_f32, double2 *lds, double *vel,
+                                                const void *__restrict__ vi, int vi_f32, double2 *lds,
                                                 Rec1 *crec, Rec1 *copen, const SchemeDev &S, const Coef1D &ci,
                                                 Store *__restrict__ psi, int m,
                                                 int K, int rec_steps, int step_base, int apply_opening)
@@ -87,12 +87,12 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
     const double lo = I.lo[0], dx = I.dx[0], eps = I.eps;
     const VFac vf = I.vf[0];
     Store *base = psi + I.offset;
-    double *ve = vel + slot * N + tl;
+    double ve[P];  // eps V_I at the thread's points, in registers
 #pragma unroll
     for (int c = 0; c < P; ++c) {
         const int i = tl + c * T;
         const double x = lo + (double)i * dx;
-        ve[c * T] = vi ? vi_at(vi, vi_f32, I.offset + i) : eps * vfactor(vf, x);
+        ve[c] = vi ? vi_at(vi, vi_f32, I.offset + i) : eps * vfactor(vf, x);
         u[c] = active ? to_d2(base[i]) : make_double2(0.0, 0.0);
     }
     __syncthreads();  // cis table in LDS
@@ -103,7 +103,7 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
         for (int c = 0; c < P; ++c) {
             const double x = lo + (double)(tl + c * T) * dx;
             const double a2 = fma(u[c].x, u[c].x, u[c].y * u[c].y);
-            th[c] = fma(chi, 0.5 * x * x, fma(w, ve[c * T], s * a2));
+            th[c] = fma(chi, 0.5 * x * x, fma(w, ve[c], s * a2));
         }
         cis_apply_batch<P>(u, th, ctab);
     };
@@ -211,7 +211,6 @@ __global__ __launch_bounds__(kThreads1D, 2) void hf1d_fixed_kernel(const Item1D 
     constexpr int NOPEN = (RULE < 0) ? 1 : kThreads1D / 8;
     __shared__ double2 lds[LDS_ELEMS];
     __shared__ CisTable ctab;
-    __shared__ double vel[kThreads1D * 8];
     __shared__ Rec1 crec[NREC];
     __shared__ Rec1 copen[NOPEN];
     // the scheme in LDS: the record phases read it after a barrier each time
@@ -226,7 +225,7 @@ __global__ __launch_bounds__(kThreads1D, 2) void hf1d_fixed_kernel(const Item1D 
     load_cis_table(&ctab, cistab);
     const Item1D it = items[blockIdx.x];
 #define HFGPE_1D_BODY(LG)                                                                                         \
-    hf1d_fixed_body<Store, LG, RULE>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, vel, crec, copen, sch[0], ci, \
+    hf1d_fixed_body<Store, LG, RULE>(it, perm, insts, rec, rec_open, ctab, vi, vi_f32, lds, crec, copen, sch[0], ci, \
                                      psi, m, K, rec_steps, step_base, apply_opening)
     switch (it.logn) {
     case 6: HFGPE_1D_BODY(6); break;
