@@ -65,14 +65,15 @@ def progress(msg):
 
 def timed_evolve(pkg, torch, w, dtype, K, warmup, **kw):
     plan = pkg.Plan(w.instances, w.scheme, w.ho_rule, dtype, w.dt, profile=True, **kw)
+    # both buffers are packed first, so the timed call follows the warm-up
+    # steps without the host-to-device copy in between
+    buf = plan.pack(w.psi0)
     if warmup > 0:
         scratch = plan.pack(w.psi0)
-        plan.evolve(scratch, 0.0, warmup)
         torch.cuda.synchronize()
-        del scratch
-    plan.profile()  # reset counters
-    buf = plan.pack(w.psi0)
+        plan.evolve(scratch, 0.0, warmup)
     torch.cuda.synchronize()
+    plan.profile()  # reset counters
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
