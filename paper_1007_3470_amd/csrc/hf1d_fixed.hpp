@@ -36,10 +36,11 @@ struct Coef1D {
     int *err;
 };
 
-// The records of steps step_base + b0 + s (s < kb) of the group's `count`
+// The records of the chunk's steps s0 + s (s < kb) of the group's `count`
 // instances into crec[(j kb + s) m + i], one step per thread, and the opening
-// record of instance slot j into copen[j] when step 0 is among them.  Kept
-// out of line: the step loop's register allocation does not see this code.
+// record of instance slot j into copen[j] when global step 0 is among them.
+// Kept out of line: the step loop's register allocation does not see this
+// code.
 template <int RULE>
 __device__ __noinline__ void eval_records_1d(int first, int count, const int *__restrict__ perm,
                                              const InstDev *__restrict__ insts, const SchemeDev &S,
