@@ -181,7 +181,7 @@ struct Fft1D {
 // addresses of all passes fold into instruction offsets instead of occupying
 // registers across the step loop.  The padding algebra used below:
 // pad(x + y) = pad(x) + y + (y >> 3) whenever (x mod 8) + (y mod 8) < 8.
-template <int LOGN, typename Xch = double2>
+template <int LOGN, typename Xch = double2, int NBUF = 1, int BSTRIDE = 0>
 struct FftFix8 {
     static constexpr int P = 8, LOGP = 3;
     static constexpr int N = 1 << LOGN;
@@ -234,9 +234,20 @@ struct FftFix8 {
         }
     }
 
-    template <int SGN>
+    // With NBUF = 2 the passes alternate between two buffers BSTRIDE elements
+    // apart: pass s reads the buffer pass s - 1 wrote and writes the other,
+    // so one barrier per pass suffices (a pass writes the buffer the previous
+    // pass read, and every wave has finished those reads at the barrier
+    // before its own reads).  Pass 0 writes buffer START; the call after this
+    // one must start at next_start(START), the buffer the last pass did not
+    // read, since nothing separates the last reads from the next writes.
+    static constexpr int next_start(int start) { return (NBUF == 2) ? ((start + S - 1) & 1) : 0; }
+
+    template <int SGN, int START = 0>
     __device__ __forceinline__ void run(double2 *u)
     {
+        static_assert(NBUF == 1 || NBUF == 2, "one or two exchange buffers");
+        constexpr auto buf = [](int k) { return (NBUF == 2) ? (k & 1) * BSTRIDE : 0; };
         // pass 0: radix R0 on the thread's own points {t + cT}
         constexpr int NB = P / R0;
         constexpr int BSTR = T * R0 + ((T * R0) >> 3);
@@ -247,14 +258,14 @@ struct FftFix8 {
             for (int r = 0; r < R0; ++r) v[r] = u[b + r * NB];
             Dft<R0, SGN>::run(v);
 #pragma unroll
-            for (int rp = 0; rp < R0; ++rp) lds[w0off + b * BSTR + rp] = from_d2<Xch>(v[rp]);
+            for (int rp = 0; rp < R0; ++rp) lds[buf(START) + w0off + b * BSTR + rp] = from_d2<Xch>(v[rp]);
         }
 #pragma unroll
         for (int s = 1; s < S; ++s) {
             __syncthreads();
 #pragma unroll
-            for (int c = 0; c < P; ++c) u[c] = to_d2(lds[roff + c * TP]);
-            __syncthreads();
+            for (int c = 0; c < P; ++c) u[c] = to_d2(lds[buf(START + s - 1) + roff + c * TP]);
+            if constexpr (NBUF == 1) __syncthreads();
             const double2 w1 = tw[s - 1][0], w2 = tw[s - 1][1], w4 = tw[s - 1][2];
             const double2 w3 = cmul(w1, w2);
             const double2 w[7] = {w1, w2, w3, w4, cmul(w1, w4), cmul(w2, w4), cmul(w3, w4)};
@@ -264,7 +275,8 @@ struct FftFix8 {
             if (s < S - 1) {
                 const int L = 1 << (R0LOG + LOGP * (s - 1));
 #pragma unroll
-                for (int rp = 0; rp < P; ++rp) lds[woff[s - 1] + rp * L + ((rp * L) >> 3)] = from_d2<Xch>(u[rp]);
+                for (int rp = 0; rp < P; ++rp)
+                    lds[buf(START + s) + woff[s - 1] + rp * L + ((rp * L) >> 3)] = from_d2<Xch>(u[rp]);
             }
         }
     }

@@ -21,6 +21,13 @@
 
 namespace hfgpe {
 
+// FFT exchange buffer of a workgroup: 256 threads x 8 points, one padding
+// element in 8.  Two of them: the passes alternate between the two, which
+// takes one barrier per pass instead of two (two workgroups per CU still fit
+// the 160 KB of LDS: 78 KB of buffers and the 6 KB phase table each).
+constexpr int kLds1D = kThreads1D * 8 + ((kThreads1D * 8) >> kPadShift);
+constexpr int kNbuf1D = 2;
+
 // the part of a stage record a 1-D step uses
 struct Rec1 {
     double g, chi, w, s;
@@ -71,7 +78,7 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
                                                 Store *__restrict__ psi, int m,
                                                 int K, int rec_steps, int step_base, int apply_opening)
 {
-    using F = FftFix8<LOGN>;
+    using F = FftFix8<LOGN, double2, kNbuf1D, kLds1D>;
     constexpr int P = 8, N = F::N, T = F::T;
     const int tid = threadIdx.x;
     const int slot = tid >> F::LOGT;
@@ -143,10 +150,14 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
             if (c > P / 2) E = cmul(E, Q);
         }
     };
+    // the forward transform starts in exchange buffer 0, the inverse where the
+    // forward left off, and the next stage's forward in buffer 0 again
+    constexpr int kInvStart = F::next_start(0);
+    static_assert(F::next_start(kInvStart) == 0, "exchange buffers");
     auto stage = [&](double g, double chi, double w, double s) {
-        fft.template run<-1>(u);
+        fft.template run<-1, 0>(u);
         drift(g);
-        fft.template run<+1>(u);
+        fft.template run<+1, kInvStart>(u);
         xphase(chi, w, s);
     };
 
@@ -177,6 +188,7 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < P; ++c) u[c] = park[c * F::TP];
+            __syncthreads();  // every parked value is read before a first pass overwrites the buffer
             if (b0 == 0 && apply_opening) {
                 const Rec1 o = copen[rslot];
                 xphase(o.chi, o.w, o.s);
@@ -207,10 +219,9 @@ __global__ __launch_bounds__(kThreads1D, 2) void hf1d_fixed_kernel(const Item1D 
                                                                 Coef1D ci, Store *__restrict__ psi, int m, int K,
                                                                 int rec_steps, int step_base, int apply_opening)
 {
-    constexpr int LDS_ELEMS = kThreads1D * 8 + ((kThreads1D * 8) >> kPadShift);
     constexpr int NREC = (RULE < 0) ? 1 : kRecLds1D;
     constexpr int NOPEN = (RULE < 0) ? 1 : kThreads1D / 8;
-    __shared__ double2 lds[LDS_ELEMS];
+    __shared__ double2 lds[kNbuf1D * kLds1D];
     __shared__ CisTable ctab;
     __shared__ Rec1 crec[NREC];
     __shared__ Rec1 copen[NOPEN];
