@@ -150,8 +150,9 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
             if (c > P / 2) E = cmul(E, Q);
         }
     };
-    // the forward transform starts in exchange buffer 0, the inverse where the
-    // forward left off, and the next stage's forward in buffer 0 again
+    // the forward transform starts in exchange buffer 0, the inverse in the
+    // buffer the forward's last pass did not read, and the next stage's
+    // forward in buffer 0 again (the park area of the in-kernel records)
     constexpr int kInvStart = F::next_start(0);
     static_assert(F::next_start(kInvStart) == 0, "exchange buffers");
     auto stage = [&](double g, double chi, double w, double s) {
