@@ -403,3 +403,33 @@ def test_one_point_grid_stage_time_quadrature(pkg, dtype, tol, scheme):
         err = abs(got[k][0] - ex) / abs(ex)
         say("one-point %s %s sigma form %d: %.3e" % (scheme, dtype, form, err))
         assert err < tol, (k, err)
+
+
+# ---------------------------------------------------------------------------
+# large drift angles: the fixed-shape kernel forms the drift factors
+# exp(-i g k^2/2) of a thread's points from three table evaluations by a
+# quadratic recurrence; on fine grids with broadband states the angles reach
+# hundreds of radians, where every evaluation's error is set by the rounding of
+# the angle itself (about theta * 2^-53 per factor, in the oracle's direct
+# evaluation too)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_large_drift_angles_broadband(pkg, dtype):
+    rng = np.random.default_rng(77)
+    insts, psis = [], []
+    for n, half in ((256, 2.0), (512, 2.0), (1024, 3.0), (2048, 4.0)):
+        inst = W.Instance(1, (n, 1, 1), (-half, 0.0, 0.0), (half, 1.0, 1.0), omega=((1.3, 0.0, 0.0, 0.0),) + (W.CONST_OMEGA,) * 2)
+        u = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        insts.append(inst)
+        psis.append(W._normalise(inst, u))
+    dt, nsteps = 1e-3, 200
+    w = W.Workload("broadband", insts, psis, "leapfrog", "exact_const", dt, nsteps)
+    _, _, got = run_gpu(pkg, w, dtype)
+    for k, inst in enumerate(insts):
+        kmax = math.pi * inst.n[0] / (inst.hi[0] - inst.lo[0])
+        theta = dt * kmax * kmax / 2.0
+        bound = nsteps * theta * 8 * 2.0 ** -53 if dtype == "c128" else 5e-5
+        ref = oracle_run(w, k)
+        err = W.rel_l2(got[k], ref)
+        say("broadband N=%d max drift angle %.0f rad: %s rel_l2 %.3e (bound %.1e)" % (inst.n[0], theta, dtype, err, bound))
+        assert err < max(bound, 1e-11)
