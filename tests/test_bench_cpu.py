@@ -1,6 +1,7 @@
 """Host logic of bench.py (no GPU): the kernel-source hashes that decide
 whether stored HBM counters still describe the measured kernels, the stored
-counters' lookup, the algorithmic flop count and the single-GPU guard."""
+counters' lookup, the algorithmic flop count, the single-GPU guard and the bounded
+oracle sample."""
 import json
 import math
 import os
@@ -84,3 +85,22 @@ def test_nd_passes_per_step():
     assert bench.nd_passes_per_step(pkg, W.coupled_2d(n=16, n_inst=1, nsteps=1, rule="fsplit")) == 2
     assert bench.nd_passes_per_step(pkg, W.coupled_2d(n=16, n_inst=1, nsteps=1, rule="exact_const",
                                                       constant=True)) == 3
+
+
+def test_cpu_baseline_runs_a_bounded_sample():
+    """The oracle leg runs the benchmark's K steps on every sampled instance,
+    then continues the same instances until about target_s seconds have run,
+    and reports the rate over every step it ran."""
+    import workloads as W
+    w = W.batch_1d(n_inst=12, sizes=(256, 512), nsteps=3, seed=5)
+    t0 = bench.time.perf_counter()
+    cpu, errs = bench.cpu_baseline(w, 3, 2, {}, target_s=0.4)
+    wall = bench.time.perf_counter() - t0
+    assert errs == {}
+    assert cpu["kind"] == "oracle" and cpu["unit"] == "grid-point-steps/s"
+    assert 1 <= cpu["cores"] <= 16 and cpu["value"] > 0
+    steps = int(re.search(r"x (\d+) steps", cpu["sample"]).group(1))
+    assert steps >= 3
+    # the sample is 2 instances per size, about 0.4 s of work: not far beyond
+    assert re.match(r"4 instances \(2 per grid size\)", cpu["sample"])
+    assert wall < 10.0
