@@ -208,8 +208,9 @@ typedef struct {
                               64..2048 evaluates the stage coefficients inside
                               the resident step kernel, per block of steps, with
                               the coefficient kernel's arithmetic (the same bits
-                              in FP64): no record table traffic and no chunks,
-                              but each workgroup waits for its records, so it is
+                              in FP64): no record table traffic and launches of
+                              up to 16384 steps whatever the batch size, but
+                              each workgroup waits for its records, so it is
                               slower on batches of many workgroups; 0 (default)
                               = a coefficient kernel writes a record table
                               before each chunk (always so for d-D plans, host

@@ -1214,8 +1214,9 @@ int hfgpe_instance_offsets(const hfgpe_plan *plan, int64_t *off)
     return HFGPE_OK;
 }
 
-// steps per launch sequence when the records are evaluated in the kernel
-constexpr int kFusedChunkMax = 1 << 30;
+// steps per resident launch when the records are evaluated in the kernel: no
+// record table bounds it, so the table's step cap bounds each launch's length
+constexpr int kFusedChunkMax = (int)kRecStepsMax;
 
 // In-kernel stage records: asked for, on a 1-D plan without host callbacks,
 // not on the plain schedule, whose every group runs the fixed-shape kernel.
@@ -1238,7 +1239,7 @@ int hfgpe_evolve(hfgpe_plan *P, void *d_psi, double t0, int64_t nsteps)
     const bool plain = P->opts.plain != 0;
     // on request, 1-D plans whose groups all take the fixed-shape kernel
     // evaluate the stage records inside the step kernel: no coefficient
-    // kernel, no record table traffic, no chunking
+    // kernel and no record table traffic
     const bool fused = fused_records_1d(*P);
     int chunk = (int)std::min<int64_t>(nsteps, fused ? kFusedChunkMax
                                                      : (host_records ? P->cb_steps_cap : P->rec_steps_cap));

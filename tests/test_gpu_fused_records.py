@@ -124,3 +124,16 @@ def test_plan_with_a_generic_size_uses_the_table(pkg):
     a = run(pkg, w, "c128", True)
     b = run(pkg, w, "c128", False)
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_in_kernel_records_across_launches_of_16384_steps(pkg):
+    """Evolve calls longer than 16384 steps run as several resident launches
+    (the records of each start at its global step, the opening phase only in
+    the first); the bits match the record-table path."""
+    w = mixed_batch("cf4", "leapfrog", seed=23)
+    w = replace(w, instances=w.instances[36:44], psi0=w.psi0[36:44], nsteps=16384 + 37, dt=2e-5)
+    a = run(pkg, w, "c128", True)
+    b = run(pkg, w, "c128", False)
+    worst = max(float(np.max(np.abs(x - y))) for x, y in zip(a, b))
+    say("16421 steps: max |in-kernel - table| %.3e" % worst)
+    assert worst == 0.0
