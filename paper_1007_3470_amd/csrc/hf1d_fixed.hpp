@@ -22,11 +22,14 @@
 namespace hfgpe {
 
 // FFT exchange buffer of a workgroup: 256 threads x 8 points, one padding
-// element in 8.  Two of them: the passes alternate between the two, which
-// takes one barrier per pass instead of two (two workgroups per CU still fit
-// the 160 KB of LDS: 78 KB of buffers and the 6 KB phase table each).
+// element in 8.  Two of them with records from the table: the passes
+// alternate between the two, which takes one barrier per pass instead of two
+// (two workgroups per CU still fit the 160 KB of LDS: 72 KB of buffers and the
+// 6 KB phase table each).  One with in-kernel records, whose 17 KB of record
+// blocks would otherwise leave room for one workgroup per CU.
 constexpr int kLds1D = kThreads1D * 8 + ((kThreads1D * 8) >> kPadShift);
-constexpr int kNbuf1D = 2;
+template <int RULE>
+constexpr int nbuf_1d() { return RULE < 0 ? 2 : 1; }
 
 // the part of a stage record a 1-D step uses
 struct Rec1 {
@@ -78,7 +81,7 @@ __device__ __forceinline__ void hf1d_fixed_body(const Item1D &it, const int *__r
                                                 Store *__restrict__ psi, int m,
                                                 int K, int rec_steps, int step_base, int apply_opening)
 {
-    using F = FftFix8<LOGN, double2, kNbuf1D, kLds1D>;
+    using F = FftFix8<LOGN, double2, nbuf_1d<RULE>(), kLds1D>;
     constexpr int P = 8, N = F::N, T = F::T;
     const int tid = threadIdx.x;
     const int slot = tid >> F::LOGT;
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(kThreads1D, 2) void hf1d_fixed_kernel(const Item1D 
 {
     constexpr int NREC = (RULE < 0) ? 1 : kRecLds1D;
     constexpr int NOPEN = (RULE < 0) ? 1 : kThreads1D / 8;
-    __shared__ double2 lds[kNbuf1D * kLds1D];
+    __shared__ double2 lds[nbuf_1d<RULE>() * kLds1D];
     __shared__ CisTable ctab;
     __shared__ Rec1 crec[NREC];
     __shared__ Rec1 copen[NOPEN];
